@@ -1,0 +1,77 @@
+// Launch interface of the HIP kernels (host side, C++ linkage).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace dgk {
+
+constexpr int kWave = 64;
+constexpr int kMaxN = 9;
+constexpr int kRing = 1024;   // diagnostics records per device ring
+
+// v-elements covered by one wave for n nodes: the wave's lanes hold the
+// contiguous v-nodes of whole elements.
+inline int tv_of(int n) { return kWave / n; }
+
+// Reference operators and per-run scalars in the compute precision, passed by
+// value (kernel-argument segment, read through the scalar cache).
+template <typename T>
+struct Ops {
+  T ups[kMaxN * kMaxN];   // Upsilon, row = output node
+  T xl[kMaxN];            // Xi, left-face column
+  T xr[kMaxN];            // Xi, right-face column
+};
+
+template <typename T>
+struct StageArgs {
+  const T* fin;           // argument of L (u^(k-1))
+  const T* fun;           // u^n, read only when c_un != 0
+  T* out;                 // c_un u^n + c_in fin + c_dt L(fin)
+  const double* E;        // Nx*n field at the x nodes
+  const T* ucoord;        // Nu*n u-node coordinates (nv = 2)
+  const T* vcoord;        // Nv*n v-node coordinates
+  const double* wu;       // Nu*n u quadrature weights (dx/2 w_j), nv = 2
+  const double* wv;       // Nv*n v quadrature weights
+  const double* wx;       // Nx*n x quadrature weights (moments only)
+  double* partials;       // density partials or nullptr
+  int Nx, Nu, Nv, nvchunks;
+  int zero_inflow;        // 1: zero outside the velocity box
+  T Jx, Ju, Jv, wc;       // Jacobians 2/dx per axis, omega_c
+  T c_un, c_in, c_dt;     // stage coefficients
+};
+
+template <typename T>
+struct StagePack {
+  StageArgs<T> a;
+  Ops<T> op;
+};
+
+struct FieldArgs {
+  const double* partials;  // [(Nx*n) * ntiles]
+  int ntiles;              // partials per x node
+  int Nx, n, pmax;
+  const double* T;         // connection tensor, complex (re,im), [(pmax) x (Nx*n)]
+  const double* G;         // synthesis table, complex, [(pmax) x (Nx*n)]
+  const double* wx;        // Nx*n x quadrature weights
+  double* dens;            // Nx*n density
+  double* cpart;           // Nx * pmax complex partial Fourier sums
+  double* mpart;           // Nx mass partials
+  double* E;               // Nx*n field out
+  double* coeffs;          // pmax complex coefficients out
+  double* ring;            // diagnostics ring (dg_diag records as 8 doubles) or nullptr
+  double* last;            // always receives the newest record (8 doubles)
+  int* counter;            // ring write counter
+  int record;              // 1: append a record
+};
+
+// Launchers return hipSuccess or the launch error.  `args` points to a
+// StagePack<float> or StagePack<double> matching f64.
+hipError_t launch_stage(int nv, int n, bool f64, const void* args, int ntiles, hipStream_t s);
+hipError_t launch_density(int nv, int n, bool f64, const void* args, int ntiles, hipStream_t s);
+hipError_t launch_moments(int nv, int n, bool f64, const void* args, double* mom, int ntiles, hipStream_t s);
+hipError_t launch_field(const FieldArgs& a, hipStream_t s);
+hipError_t launch_moments_reduce(const double* mom, int ntiles, double* ring, const int* counter, hipStream_t s);
+hipError_t launch_reset_counter(int* counter, hipStream_t s);
+
+}  // namespace dgk

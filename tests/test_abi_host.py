@@ -1,0 +1,102 @@
+"""C-ABI checks that need no GPU: exported symbols and the FP64 host setup."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import cfl, grid, lgl, poisson
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+dg = pytest.importorskip("paper_2202_13532_amd.dg")
+
+
+def _lib():
+    if not os.path.exists(dg.LIB_PATH):
+        pytest.fail("libdg.so is not built (run __graft_entry__.build())")
+    return dg.lib()
+
+
+def _declared_functions():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(dg_[a-z0-9_]+)\s*\(", txt, re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    names = _declared_functions()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(dg.EXPORTED) <= set(names)
+
+
+@pytest.mark.parametrize("n", range(2, 10))
+def test_host_basis_matches_oracle(n):
+    _lib()
+    b = dg.dg_basis(n)
+    o = lgl.operators(n)
+    assert np.max(np.abs(b["xi"] - o["xi"])) < 1e-15
+    assert np.max(np.abs(b["w"] - o["w"])) < 1e-15
+    # library: closed forms (eq. num_flux_wow); oracle: M^-1 S products
+    assert np.max(np.abs(b["Ups"] - o["Ups"])) < 1e-13 * n * n
+    assert np.max(np.abs(b["Xi"] - o["Xi"])) < 1e-13 * n
+    assert np.max(np.abs(b["D"] - o["D"])) < 1e-13 * n * n
+
+
+@pytest.mark.parametrize("n,N,L,pmax", [(2, 5, 1.0, 5), (4, 16, 4 * math.pi, 16), (8, 32, 40 * math.pi, 32),
+                                         (9, 64, 20 * math.pi, 64), (6, 7, 3.0, 20)])
+def test_host_connection_tensor_matches_oracle_quadrature(n, N, L, pmax):
+    _lib()
+    T = dg.dg_connection_tensor(n, N, 0.0, L, pmax)
+    To, ps, _ = poisson.connection_tensor(grid.Axis(0.0, L, N, n), pmax)
+    assert np.max(np.abs(T - To[pmax + 1:])) < 1e-15
+
+
+@pytest.mark.parametrize("n", range(2, 10))
+def test_host_courant_number_matches_oracle(n):
+    _lib()
+    assert abs(dg.dg_courant_number(n) / cfl.courant_number(n) - 1) < 2e-5
+
+
+def test_workspace_bytes_and_config_validation():
+    _lib()
+    ok = dg.make_config(2, 8, [32, 32, 32], [0, -8, -8], [4 * math.pi, 8, 8], 1.0)
+    nb = dg.dg_workspace_bytes(ok)
+    dof = (32 * 8) ** 3
+    assert nb >= 2 * dof * 4 and nb < 2 * dof * 4 + 64 * 2 ** 20
+    assert dg.dg_workspace_bytes(dg.make_config(2, 8, [32, 32, 32], [0, -8, -8], [4 * math.pi, 8, 8], 1.0, storage="f64")) > 2 * dof * 8
+    bad = [dg.make_config(3, 4, [4, 4, 4], [0, 0, 0], [1, 1, 1]),
+           dg.make_config(1, 1, [4, 4], [0, 0], [1, 1]),
+           dg.make_config(1, 4, [0, 4], [0, 0], [1, 1]),
+           dg.make_config(1, 4, [4, 4], [0, 1], [1, 1]),
+           dg.make_config(1, 4, [4, 4], [0, 0], [1, 1], omega_c=1.0),
+           dg.make_config(2, 10, [4, 4, 4], [0, 0, 0], [1, 1, 1])]
+    for c in bad:
+        assert dg.dg_workspace_bytes(c) == 0
+
+
+def test_init_rejects_bad_arguments_before_touching_a_device():
+    _lib()
+    import ctypes
+    ctx = ctypes.c_void_p()
+    bad = dg.make_config(1, 4, [4, 4], [0, 1], [1, 1])
+    st = dg.lib().dg_init(ctypes.byref(bad), ctypes.c_void_p(256), 1 << 20, None, ctypes.byref(ctx))
+    assert st == dg.DG_ERR_INVALID and "lo < hi" in dg.dg_last_error(None)
+    good = dg.make_config(1, 4, [4, 4], [0, -1], [1, 1])
+    st = dg.lib().dg_init(ctypes.byref(good), ctypes.c_void_p(256), 16, None, ctypes.byref(ctx))
+    assert st == dg.DG_ERR_OOM
+    st = dg.lib().dg_init(ctypes.byref(good), None, 1 << 30, None, ctypes.byref(ctx))
+    assert st == dg.DG_ERR_INVALID
+    n10 = dg.make_config(1, 10, [4, 4], [0, -1], [1, 1])
+    st = dg.lib().dg_init(ctypes.byref(n10), ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(ctx))
+    assert st == dg.DG_ERR_UNSUPPORTED
+    # entry points on a NULL context fail cleanly
+    assert dg.lib().dg_rhs(None, None, None, None) == dg.DG_ERR_INVALID
+    assert dg.lib().dg_rk_step(None, None, 0.1, 1, None) == dg.DG_ERR_INVALID
+    assert dg.lib().dg_dt_max(None, 0.0) == 0.0

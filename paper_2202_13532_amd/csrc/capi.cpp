@@ -30,7 +30,7 @@ struct Layout {
   int naxes = 0, n = 0, Nx = 0, Nu = 1, Nv = 0, nvchunks = 0, pmax = 0;
   int ntiles_slab = 0, ntiles = 0;
   size_t off_B, off_C, off_part, off_mom, off_dens, off_E, off_cpart, off_mpart, off_coef, off_ring,
-      off_last, off_ctr, off_T, off_G, off_wx, off_wu, off_wv, off_uc, off_vc, total;
+      off_last, off_ctr, off_T, off_G, off_wx, off_wu, off_wv, off_uc, off_vc, off_uc64, off_vc64, total;
 };
 
 const char* validate(const dg_config* c) {
@@ -86,6 +86,8 @@ Layout make_layout(const dg_config* c) {
   L.off_wv = take(static_cast<size_t>(L.Nv) * L.n * 8);
   L.off_uc = take(static_cast<size_t>(L.Nu) * L.n * L.esize);
   L.off_vc = take(static_cast<size_t>(L.Nv) * L.n * L.esize);
+  L.off_uc64 = take(static_cast<size_t>(L.Nu) * L.n * 8);
+  L.off_vc64 = take(static_cast<size_t>(L.Nv) * L.n * 8);
   L.total = o;
   return L;
 }
@@ -162,6 +164,8 @@ void fill_pack(const dg_ctx* c, dgk::StagePack<T>* p, const void* fin, const voi
   a.wu = c->at<const double>(L.off_wu);
   a.wv = c->at<const double>(L.off_wv);
   a.wx = c->at<const double>(L.off_wx);
+  a.uc64 = c->at<const double>(L.off_uc64);
+  a.vc64 = c->at<const double>(L.off_vc64);
   a.partials = partials;
   a.Nx = L.Nx;
   a.Nu = L.Nu;
@@ -415,7 +419,9 @@ dg_status dg_init(const dg_config* cfg, void* workspace, size_t workspace_bytes,
       (e = up(L.off_T, T.data(), T.size() * 16)) != hipSuccess ||
       (e = up(L.off_G, G.data(), G.size() * 16)) != hipSuccess ||
       (e = (c->f64() ? up(L.off_uc, uc.data(), uc.size() * 8) : up(L.off_uc, ucf.data(), ucf.size() * 4))) != hipSuccess ||
-      (e = (c->f64() ? up(L.off_vc, vc.data(), vc.size() * 8) : up(L.off_vc, vcf.data(), vcf.size() * 4))) != hipSuccess)
+      (e = (c->f64() ? up(L.off_vc, vc.data(), vc.size() * 8) : up(L.off_vc, vcf.data(), vcf.size() * 4))) != hipSuccess ||
+      (e = up(L.off_uc64, uc.data(), uc.size() * 8)) != hipSuccess ||
+      (e = up(L.off_vc64, vc.data(), vc.size() * 8)) != hipSuccess)
     return cleanup(e, "upload of setup tables");
   if ((e = dgk::launch_reset_counter(c->at<int>(L.off_ctr), c->stream)) != hipSuccess) return cleanup(e, "counter reset");
   if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return cleanup(e, "hipStreamSynchronize");

@@ -34,6 +34,8 @@ struct StageArgs {
   const double* wu;       // Nu*n u quadrature weights (dx/2 w_j), nv = 2
   const double* wv;       // Nv*n v quadrature weights
   const double* wx;       // Nx*n x quadrature weights (moments only)
+  const double* uc64;     // Nu*n u-node coordinates in FP64 (moments only)
+  const double* vc64;     // Nv*n v-node coordinates in FP64 (moments only)
   double* partials;       // density partials or nullptr
   int Nx, Nu, Nv, nvchunks;
   int zero_inflow;        // 1: zero outside the velocity box

@@ -208,7 +208,8 @@ __global__ void __launch_bounds__(kWave) stage2v_kernel(StageArgs<T> a, Ops<T> o
       double s = 0.0;
 #pragma unroll
       for (int ju = 0; ju < N; ++ju) s = __builtin_fma(a.wu[iu * N + ju], static_cast<double>(f[jx][ju]), s);
-      s = wave_sum(s * wvl);
+      // lanes past the ragged end of the chunk hold garbage: select, never multiply by 0
+      s = wave_sum(act ? s * wvl : 0.0);
       if (lane == 0) a.partials[static_cast<size_t>(ix * N + jx) * ntiles + iu * a.nvchunks + vc] = s;
     }
   }
@@ -312,7 +313,7 @@ __global__ void __launch_bounds__(kWave) stage1v_kernel(StageArgs<T> a, Ops<T> o
     const double wvl = act ? a.wv[iv0 * N + jl] : 0.0;
 #pragma unroll
     for (int jx = 0; jx < N; ++jx) {
-      const double s = wave_sum(wvl * static_cast<double>(f[jx]));
+      const double s = wave_sum(act ? wvl * static_cast<double>(f[jx]) : 0.0);
       if (lane == 0) a.partials[static_cast<size_t>(ix * N + jx) * a.nvchunks + vc] = s;
     }
   }
@@ -351,7 +352,7 @@ __global__ void __launch_bounds__(kWave) density_kernel(StageArgs<T> a) {
     } else {
       s = static_cast<double>(fin[(static_cast<size_t>(ix) * N + jx) * NVn]);
     }
-    s = wave_sum(s * wvl);
+    s = wave_sum(act ? s * wvl : 0.0);
     if (lane == 0) a.partials[static_cast<size_t>(ix * N + jx) * ntiles + iu * a.nvchunks + vc] = s;
   }
 }
@@ -376,7 +377,7 @@ __global__ void __launch_bounds__(kWave) moments_kernel(StageArgs<T> a, double* 
   const size_t NUn = static_cast<size_t>(NV == 2 ? a.Nu : 1) * N;
   const T* __restrict__ fin = a.fin + static_cast<size_t>(iv0) * N + jl;
   const double wvl = act ? a.wv[iv0 * N + jl] : 0.0;
-  const double v = static_cast<double>(a.vcoord[iv0 * N + jl]);
+  const double v = a.vc64[iv0 * N + jl];
   double m = 0.0, k = 0.0, l2 = 0.0, bad = 0.0;
   for (int jx = 0; jx < N; ++jx) {
     const double wxv = a.wx[ix * N + jx];
@@ -386,7 +387,7 @@ __global__ void __launch_bounds__(kWave) moments_kernel(StageArgs<T> a, double* 
           : (static_cast<size_t>(ix) * N + jx) * NVn;
       const double fv = act ? static_cast<double>(fin[r]) : 0.0;
       const double wuv = NV == 2 ? a.wu[iu * N + ju] : 1.0;
-      const double u = NV == 2 ? static_cast<double>(a.ucoord[iu * N + ju]) : 0.0;
+      const double u = NV == 2 ? a.uc64[iu * N + ju] : 0.0;
       const double W = wxv * wuv * wvl;
       if (!isfinite(fv)) bad += 1.0;
       m = __builtin_fma(W, fv, m);

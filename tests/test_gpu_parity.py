@@ -90,12 +90,15 @@ def test_poisson_parity(case, storage):
     fd = _dev(f, s)
     fh = _host(fd)
     E, c = s.poisson(fd, coeffs=True)
-    Eo, co = poisson.field_from_density(g, rhs.density(g, fh))
-    assert np.max(np.abs(_host(E) - Eo.reshape(-1))) < 1e-12 * max(1.0, np.max(np.abs(Eo)))
+    dens = rhs.density(g, fh)
+    Eo, co = poisson.field_from_density(g, dens)
+    # FP64 sums of O(nodes) terms of size |n - 1|: tolerance scales with the source
+    scale = max(1.0, float(np.max(np.abs(dens - 1.0))))
+    assert np.max(np.abs(_host(E) - Eo.reshape(-1))) < 1e-12 * scale * max(1.0, np.max(np.abs(Eo)))
     ch = _host(c).reshape(-1, 2)
     pm = nelem[0]
     cref = co[pm + 1:]
-    assert np.max(np.abs(ch[:, 0] + 1j * ch[:, 1] - cref)) < 1e-13 * max(1.0, np.max(np.abs(cref)))
+    assert np.max(np.abs(ch[:, 0] + 1j * ch[:, 1] - cref)) < 1e-13 * scale
 
 
 def _landau_1d1v(n=4, nelem=(16, 32)):

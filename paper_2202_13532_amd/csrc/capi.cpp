@@ -30,7 +30,7 @@ struct Layout {
   int naxes = 0, n = 0, Nx = 0, Nu = 1, Nv = 0, nvchunks = 0, pmax = 0;
   int ntiles_slab = 0, ntiles = 0;
   size_t off_B, off_C, off_part, off_mom, off_dens, off_E, off_cpart, off_mpart, off_coef, off_ring,
-      off_last, off_ctr, off_T, off_G, off_wx, off_wu, off_wv, off_uc, off_vc, off_uc64, off_vc64, total;
+      off_last, off_ctr, off_T, off_z1, off_wx, off_wu, off_wv, off_uc, off_vc, off_uc64, off_vc64, total;
 };
 
 const char* validate(const dg_config* c) {
@@ -80,7 +80,7 @@ Layout make_layout(const dg_config* c) {
   L.off_last = take(64);
   L.off_ctr = take(sizeof(int));
   L.off_T = take(static_cast<size_t>(L.pmax) * nx * 16);
-  L.off_G = take(static_cast<size_t>(L.pmax) * nx * 16);
+  L.off_z1 = take(nx * 16);
   L.off_wx = take(nx * 8);
   L.off_wu = take(static_cast<size_t>(L.Nu) * L.n * 8);
   L.off_wv = take(static_cast<size_t>(L.Nv) * L.n * 8);
@@ -150,11 +150,11 @@ std::vector<double> axis_weights(const dgh::Basis& b, int N, double lo, double h
 }
 
 template <typename T>
-void fill_pack(const dg_ctx* c, dgk::StagePack<T>* p, const void* fin, const void* fun, void* out,
+void fill_pack(const dg_ctx* c, dgk::StageArgs<T>* p, const void* fin, const void* fun, void* out,
                const double* E, double* partials, double c_un, double c_in, double c_dt) {
   const Layout& L = c->L;
   std::memset(static_cast<void*>(p), 0, sizeof(*p));
-  auto& a = p->a;
+  auto& a = *p;
   a.fin = static_cast<const T*>(fin);
   a.fun = static_cast<const T*>(fun ? fun : fin);
   a.out = static_cast<T*>(out);
@@ -167,6 +167,7 @@ void fill_pack(const dg_ctx* c, dgk::StagePack<T>* p, const void* fin, const voi
   a.uc64 = c->at<const double>(L.off_uc64);
   a.vc64 = c->at<const double>(L.off_vc64);
   a.partials = partials;
+  a.hu = c->cfg.nv == 2 ? 0.5 * c->dx[1] : 1.0;
   a.Nx = L.Nx;
   a.Nu = L.Nu;
   a.Nv = L.Nv;
@@ -184,12 +185,6 @@ void fill_pack(const dg_ctx* c, dgk::StagePack<T>* p, const void* fin, const voi
   a.c_un = static_cast<T>(c_un);
   a.c_in = static_cast<T>(c_in);
   a.c_dt = static_cast<T>(c_dt);
-  const int n = L.n;
-  for (int i = 0; i < n; ++i) {
-    for (int k = 0; k < n; ++k) p->op.ups[i * dgk::kMaxN + k] = static_cast<T>(c->basis.ups[i * n + k]);
-    p->op.xl[i] = static_cast<T>(c->basis.xi_face[i * 2 + 0]);
-    p->op.xr[i] = static_cast<T>(c->basis.xi_face[i * 2 + 1]);
-  }
 }
 
 // One fused stage kernel: out = c_un un + c_in fin + c_dt L(fin) (L with field E).
@@ -197,11 +192,11 @@ dg_status stage(dg_ctx* c, const void* fin, const void* fun, void* out, const do
                 double* partials, double c_un, double c_in, double c_dt) {
   hipError_t e;
   if (c->f64()) {
-    dgk::StagePack<double> p;
+    dgk::StageArgs<double> p;
     fill_pack(c, &p, fin, fun, out, E, partials, c_un, c_in, c_dt);
     e = dgk::launch_stage(c->cfg.nv, c->L.n, true, &p, c->L.ntiles, c->stream);
   } else {
-    dgk::StagePack<float> p;
+    dgk::StageArgs<float> p;
     fill_pack(c, &p, fin, fun, out, E, partials, c_un, c_in, c_dt);
     e = dgk::launch_stage(c->cfg.nv, c->L.n, false, &p, c->L.ntiles, c->stream);
   }
@@ -213,11 +208,11 @@ dg_status density(dg_ctx* c, const void* f) {
   hipError_t e;
   double* part = c->at<double>(c->L.off_part);
   if (c->f64()) {
-    dgk::StagePack<double> p;
+    dgk::StageArgs<double> p;
     fill_pack(c, &p, f, f, nullptr, nullptr, part, 0, 0, 0);
     e = dgk::launch_density(c->cfg.nv, c->L.n, true, &p, c->L.ntiles, c->stream);
   } else {
-    dgk::StagePack<float> p;
+    dgk::StageArgs<float> p;
     fill_pack(c, &p, f, f, nullptr, nullptr, part, 0, 0, 0);
     e = dgk::launch_density(c->cfg.nv, c->L.n, false, &p, c->L.ntiles, c->stream);
   }
@@ -229,11 +224,11 @@ dg_status moments(dg_ctx* c, const void* f) {
   hipError_t e;
   double* mom = c->at<double>(c->L.off_mom);
   if (c->f64()) {
-    dgk::StagePack<double> p;
+    dgk::StageArgs<double> p;
     fill_pack(c, &p, f, f, nullptr, nullptr, nullptr, 0, 0, 0);
     e = dgk::launch_moments(c->cfg.nv, c->L.n, true, &p, mom, c->L.ntiles, c->stream);
   } else {
-    dgk::StagePack<float> p;
+    dgk::StageArgs<float> p;
     fill_pack(c, &p, f, f, nullptr, nullptr, nullptr, 0, 0, 0);
     e = dgk::launch_moments(c->cfg.nv, c->L.n, false, &p, mom, c->L.ntiles, c->stream);
   }
@@ -251,8 +246,9 @@ dg_status field(dg_ctx* c, double* E, double* coeffs, bool record) {
   a.Nx = L.Nx;
   a.n = L.n;
   a.pmax = L.pmax;
+  a.k1 = 2.0 * M_PI / (c->cfg.hi[0] - c->cfg.lo[0]);
   a.T = c->at<double>(L.off_T);
-  a.G = c->at<double>(L.off_G);
+  a.z1 = c->at<double>(L.off_z1);
   a.wx = c->at<double>(L.off_wx);
   a.dens = c->at<double>(L.off_dens);
   a.cpart = c->at<double>(L.off_cpart);
@@ -407,8 +403,19 @@ dg_status dg_init(const dg_config* cfg, void* workspace, size_t workspace_bytes,
   std::vector<double> wv = axis_weights(c->basis, L.Nv, cfg->lo[vax], cfg->hi[vax]);
   std::vector<double> uc = cfg->nv == 2 ? axis_nodes(c->basis, L.Nu, cfg->lo[1], cfg->hi[1]) : std::vector<double>(n, 0.0);
   std::vector<double> vc = axis_nodes(c->basis, L.Nv, cfg->lo[vax], cfg->hi[vax]);
-  auto T = dgh::connection_tensor(c->basis, L.Nx, cfg->lo[0], cfg->hi[0], L.pmax);
-  auto G = dgh::field_synthesis(c->basis, L.Nx, cfg->lo[0], cfg->hi[0], L.pmax);
+  // connection tensor stored node-major ([m*n + j][p]) so lanes over p are contiguous
+  auto Tp = dgh::connection_tensor(c->basis, L.Nx, cfg->lo[0], cfg->hi[0], L.pmax);
+  const size_t nxn = static_cast<size_t>(L.Nx) * n;
+  std::vector<std::complex<double>> T(Tp.size());
+  for (int p = 0; p < L.pmax; ++p)
+    for (size_t q = 0; q < nxn; ++q) T[q * L.pmax + p] = Tp[p * nxn + q];
+  // e^{i k_1 x_mj}: first column of the synthesis recurrence
+  std::vector<std::complex<double>> Z1(nxn);
+  {
+    std::vector<double> xn = axis_nodes(c->basis, L.Nx, cfg->lo[0], cfg->hi[0]);
+    const double k1 = 2.0 * M_PI / (cfg->hi[0] - cfg->lo[0]);
+    for (size_t q = 0; q < nxn; ++q) Z1[q] = std::polar(1.0, k1 * xn[q]);
+  }
   std::vector<float> ucf(uc.begin(), uc.end()), vcf(vc.begin(), vc.end());
   auto up = [&](size_t off, const void* src, size_t bytes) {
     return hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
@@ -417,7 +424,7 @@ dg_status dg_init(const dg_config* cfg, void* workspace, size_t workspace_bytes,
       (e = up(L.off_wu, wu.data(), wu.size() * 8)) != hipSuccess ||
       (e = up(L.off_wv, wv.data(), wv.size() * 8)) != hipSuccess ||
       (e = up(L.off_T, T.data(), T.size() * 16)) != hipSuccess ||
-      (e = up(L.off_G, G.data(), G.size() * 16)) != hipSuccess ||
+      (e = up(L.off_z1, Z1.data(), Z1.size() * 16)) != hipSuccess ||
       (e = (c->f64() ? up(L.off_uc, uc.data(), uc.size() * 8) : up(L.off_uc, ucf.data(), ucf.size() * 4))) != hipSuccess ||
       (e = (c->f64() ? up(L.off_vc, vc.data(), vc.size() * 8) : up(L.off_vc, vcf.data(), vcf.size() * 4))) != hipSuccess ||
       (e = up(L.off_uc64, uc.data(), uc.size() * 8)) != hipSuccess ||

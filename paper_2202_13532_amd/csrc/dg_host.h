@@ -28,11 +28,6 @@ double spherical_bessel_j(int s, double z);
 std::vector<std::complex<double>> connection_tensor(const Basis& b, int nelem, double lo,
                                                     double hi, int pmax);
 
-// Synthesis table G_p(x_mj) = (i / k_p) e^{i k_p x_mj}, p = 1..pmax, so that
-// E_mj = sum_p 2 Re(c_p G_p(x_mj))  (eq. electric_sol with c_{-p} = conj c_p).
-std::vector<std::complex<double>> field_synthesis(const Basis& b, int nelem, double lo,
-                                                  double hi, int pmax);
-
 // Eigenvalues of a small complex matrix (row-major, m x m).
 std::vector<std::complex<double>> eigenvalues(std::vector<std::complex<double>> a, int m);
 

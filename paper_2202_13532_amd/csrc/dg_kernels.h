@@ -14,15 +14,6 @@ constexpr int kRing = 1024;   // diagnostics records per device ring
 // contiguous v-nodes of whole elements.
 inline int tv_of(int n) { return kWave / n; }
 
-// Reference operators and per-run scalars in the compute precision, passed by
-// value (kernel-argument segment, read through the scalar cache).
-template <typename T>
-struct Ops {
-  T ups[kMaxN * kMaxN];   // Upsilon, row = output node
-  T xl[kMaxN];            // Xi, left-face column
-  T xr[kMaxN];            // Xi, right-face column
-};
-
 template <typename T>
 struct StageArgs {
   const T* fin;           // argument of L (u^(k-1))
@@ -37,24 +28,20 @@ struct StageArgs {
   const double* uc64;     // Nu*n u-node coordinates in FP64 (moments only)
   const double* vc64;     // Nv*n v-node coordinates in FP64 (moments only)
   double* partials;       // density partials or nullptr
+  double hu;              // du/2 (u-axis Jacobian inverse), nv = 2
   int Nx, Nu, Nv, nvchunks;
   int zero_inflow;        // 1: zero outside the velocity box
   T Jx, Ju, Jv, wc;       // Jacobians 2/dx per axis, omega_c
   T c_un, c_in, c_dt;     // stage coefficients
 };
 
-template <typename T>
-struct StagePack {
-  StageArgs<T> a;
-  Ops<T> op;
-};
-
 struct FieldArgs {
   const double* partials;  // [(Nx*n) * ntiles]
   int ntiles;              // partials per x node
   int Nx, n, pmax;
-  const double* T;         // connection tensor, complex (re,im), [(pmax) x (Nx*n)]
-  const double* G;         // synthesis table, complex, [(pmax) x (Nx*n)]
+  double k1;               // 2 pi / L
+  const double* T;         // connection tensor, complex (re,im), [(Nx*n) x pmax]
+  const double* z1;        // e^{i k_1 x_mj}, complex, [Nx*n]
   const double* wx;        // Nx*n x quadrature weights
   double* dens;            // Nx*n density
   double* cpart;           // Nx * pmax complex partial Fourier sums
@@ -68,7 +55,7 @@ struct FieldArgs {
 };
 
 // Launchers return hipSuccess or the launch error.  `args` points to a
-// StagePack<float> or StagePack<double> matching f64.
+// StageArgs<float> or StageArgs<double> matching f64.
 hipError_t launch_stage(int nv, int n, bool f64, const void* args, int ntiles, hipStream_t s);
 hipError_t launch_density(int nv, int n, bool f64, const void* args, int ntiles, hipStream_t s);
 hipError_t launch_moments(int nv, int n, bool f64, const void* args, double* mom, int ntiles, hipStream_t s);

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dg_kernels.h"
+#include "dg_ops_constexpr.h"
 
 namespace dgk {
 
@@ -29,38 +30,158 @@ __device__ __forceinline__ int xcd_remap(int b, int g) {
   return c * q + min(c, r) + (b >> 3);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+// Sum over the 64 lanes of a wave, result valid in every lane.  Within each
+// 16-lane row the butterfly uses DPP (quad_perm xor 1, xor 2, row_ror 4, 8),
+// so no LDS round trip is needed; the four row sums are combined through
+// readlane.  Fixed order: bitwise reproducible.
+__device__ __forceinline__ double dpp_f64(double v, int ctrl_sel) {
+  typedef int i32x2 __attribute__((ext_vector_type(2)));
+  i32x2 x = __builtin_bit_cast(i32x2, v);
+  i32x2 y;
+  switch (ctrl_sel) {
+    case 0:
+      y.x = __builtin_amdgcn_update_dpp(0, x.x, 0xB1, 0xF, 0xF, false);
+      y.y = __builtin_amdgcn_update_dpp(0, x.y, 0xB1, 0xF, 0xF, false);
+      break;
+    case 1:
+      y.x = __builtin_amdgcn_update_dpp(0, x.x, 0x4E, 0xF, 0xF, false);
+      y.y = __builtin_amdgcn_update_dpp(0, x.y, 0x4E, 0xF, 0xF, false);
+      break;
+    case 2:
+      y.x = __builtin_amdgcn_update_dpp(0, x.x, 0x124, 0xF, 0xF, false);
+      y.y = __builtin_amdgcn_update_dpp(0, x.y, 0x124, 0xF, 0xF, false);
+      break;
+    default:
+      y.x = __builtin_amdgcn_update_dpp(0, x.x, 0x128, 0xF, 0xF, false);
+      y.y = __builtin_amdgcn_update_dpp(0, x.y, 0x128, 0xF, 0xF, false);
+      break;
+  }
+  return __builtin_bit_cast(double, y);
 }
+
+__device__ __forceinline__ double lane_f64(double v, int l) {
+  typedef int i32x2 __attribute__((ext_vector_type(2)));
+  i32x2 x = __builtin_bit_cast(i32x2, v);
+  i32x2 y;
+  y.x = __builtin_amdgcn_readlane(x.x, l);
+  y.y = __builtin_amdgcn_readlane(x.y, l);
+  return __builtin_bit_cast(double, y);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64(v, 0);   // lane ^ 1
+  v += dpp_f64(v, 1);   // lane ^ 2
+  v += dpp_f64(v, 2);   // rotate by 4 within the row
+  v += dpp_f64(v, 3);   // rotate by 8 within the row: every lane holds its row sum
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
+// The stage kernels run one wave per work-group.  LDS instructions of one
+// wave execute in program order, so exchanging data through LDS between the
+// lanes of that wave only needs the compiler not to reorder the accesses; a
+// work-group barrier would also wait for every outstanding global load.
+__device__ __forceinline__ void wave_lds_order() { __asm__ volatile("" ::: "memory"); }
 
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// t_i = sum_k Ups_ik g_k + Xl_i fL - Xr_i fR  for one pencil; res_i = s t_i (+ res_i).
+// t_i = sum_k Ups_ik g_k + Xl_i fL - Xr_i fR for one pencil (operator entries
+// are compile-time literals); res_i = s t_i, or res_i += s t_i when ACC.
+//
+// Even/odd form: on the symmetric LGL nodes Upsilon is centro-antisymmetric
+// (Ups[n-1-i][n-1-k] = -Ups[i][k]) and the face columns mirror each other
+// (Xr[i] = Xl[n-1-i]).  With e_k = g_k + g_{n-1-k}, o_k = g_k - g_{n-1-k},
+// S = fL + fR, D = fL - fR and m = n/2, every output pair (i, n-1-i) is
+//   P = sum_{k<m} A_ik e_k + Ups_ic g_c + (Xl_i - Xr_i)/2 S,
+//   Q = sum_{k<m} B_ik o_k + (Xl_i + Xr_i)/2 D,
+//   t_i = P + Q,  t_{n-1-i} = Q - P,
+// A = (Ups_ik + Ups_i,n-1-k)/2, B = (Ups_ik - Ups_i,n-1-k)/2, c the middle
+// node (odd n); the middle output is sum_k B_ck o_k + Xl_c D.
 template <typename T, int N, bool ACC, typename G>
-__device__ __forceinline__ void contract(const Ops<T>& op, G g, T fL, T fR, T s, T* res) {
+__device__ __forceinline__ void contract(G g, T fL, T fR, T s, T* res) {
+  static_assert(dgc::reflection_symmetric<N>(), "LGL operators must be reflection symmetric");
+  constexpr dgc::OpsC<N> K = dgc::make_ops<N>();
+  constexpr int M = N / 2;
+  const T S = fL + fR, D = fL - fR;
+  T e[M], o[M];
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    T t = op.xl[i] * fL - op.xr[i] * fR;
+  for (int k = 0; k < M; ++k) {
+    e[k] = g(k) + g(N - 1 - k);
+    o[k] = g(k) - g(N - 1 - k);
+  }
 #pragma unroll
-    for (int k = 0; k < N; ++k) t = fmadd(op.ups[i * kMaxN + k], g(k), t);
-    res[i] = ACC ? fmadd(s, t, res[i]) : s * t;
+  for (int i = 0; i < M; ++i) {
+    T P = static_cast<T>(0.5 * (K.xl[i] - K.xr[i])) * S;
+#pragma unroll
+    for (int k = 0; k < M; ++k) P = fmadd(static_cast<T>(0.5 * (K.ups[i][k] + K.ups[i][N - 1 - k])), e[k], P);
+    if (N % 2) P = fmadd(static_cast<T>(K.ups[i][M]), g(M), P);
+    T Q = static_cast<T>(0.5 * (K.xl[i] + K.xr[i])) * D;
+#pragma unroll
+    for (int k = 0; k < M; ++k) Q = fmadd(static_cast<T>(0.5 * (K.ups[i][k] - K.ups[i][N - 1 - k])), o[k], Q);
+    const T ti = P + Q, tm = Q - P;
+    res[i] = ACC ? fmadd(s, ti, res[i]) : s * ti;
+    res[N - 1 - i] = ACC ? fmadd(s, tm, res[N - 1 - i]) : s * tm;
+  }
+  if (N % 2) {
+    T Q = static_cast<T>(K.xl[M]) * D;
+#pragma unroll
+    for (int k = 0; k < M; ++k) Q = fmadd(static_cast<T>(K.ups[M][k]), o[k], Q);
+    res[M] = ACC ? fmadd(s, Q, res[M]) : s * Q;
   }
 }
 
-// -------------------------------------------------------------------------
-// 1D2V stage kernel.  state [Nx, N, Nu, N, Nv, N].
-// -------------------------------------------------------------------------
-template <typename T, int N>
-__global__ void __launch_bounds__(kWave) stage2v_kernel(StageArgs<T> a, Ops<T> op) {
-  constexpr int TV = kWave / N;
-  constexpr int ROW = kWave + 2;   // >= TV*N + 2; lane+1 stays inside a row
-  __shared__ T lds[N * ROW];
-  __shared__ T hbuf[N * N];
+// Raw buffer access.  A resource covers one x element of a state array; the
+// per-row offset goes in the scalar offset and the lane offset in the vector
+// offset.  Lanes past the ragged end of a v chunk get an out-of-range vector
+// offset: the hardware range check returns 0 for their loads and drops their
+// stores, so no lane mask or branch is needed around memory operations.
+constexpr unsigned kRsrcWord3 = 0x00020000u;   // gfx9 raw-buffer format word
+constexpr unsigned kOffOOB = 0x80000000u;
 
-  const int lane = threadIdx.x;
+template <typename T> struct Buf;
+template <> struct Buf<float> {
+  __device__ static float ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+  }
+  __device__ static void st(float v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, vo, so, 0);
+  }
+};
+template <> struct Buf<double> {
+  __device__ static double ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+  }
+  __device__ static void st(double v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t xelem_rsrc(const T* base, size_t xstride, int ix, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base + ix * xstride), 0, static_cast<int>(bytes), kRsrcWord3);
+}
+
+// LDS row stride for the v exchange: at least TV*n + 2 and = 1 (mod 64), so
+// that with pencils numbered lane = pv*n + pr the address of node k of every
+// pencil, pr*ROW + pv*n + k = lane + k (mod 64), falls in distinct banks.
+template <int N>
+constexpr int lds_row() { return (kWave / N) * N + 2 <= 65 ? 65 : 129; }
+
+// -------------------------------------------------------------------------
+// 1D2V stage kernel.  state [Nx, N, Nu, N, Nv, N].  UN: stage reads u^n.
+// -------------------------------------------------------------------------
+template <typename T, int N, bool UN>
+__global__ void __launch_bounds__(kWave, 2) stage2v_kernel(StageArgs<T> a) {
+  using B = Buf<T>;
+  constexpr unsigned S = sizeof(T);
+  constexpr int TV = kWave / N;
+  constexpr int ROW = lds_row<N>();
+  __shared__ T lds[3 * (N + 1) * ROW]; // input rows + 2 result buffers; row N of each: scratch of idle lanes
+  __shared__ T hbuf[N * N];
+  constexpr dgc::OpsC<N> K = dgc::make_ops<N>();
+
+  const unsigned lane = threadIdx.x;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int vc = bid % a.nvchunks;
   const int t1 = bid / a.nvchunks;
@@ -68,252 +189,291 @@ __global__ void __launch_bounds__(kWave) stage2v_kernel(StageArgs<T> a, Ops<T> o
   const int ix = t1 / a.Nu;
   const int iv0 = vc * TV;
   const int tva = min(TV, a.Nv - iv0);
-  const int nact = tva * N;
+  const unsigned nact = tva * N;
   const bool act = lane < nact;
-  const int jl = act ? lane : 0;
-  const size_t NVn = static_cast<size_t>(a.Nv) * N;
-  const size_t NUn = static_cast<size_t>(a.Nu) * N;
-  // first element of the row (ix, jx, iu, ju, :)
-  auto row = [&](int ixe, int jx, int iue, int ju) -> size_t {
-    return ((static_cast<size_t>(ixe) * N + jx) * NUn + static_cast<size_t>(iue) * N + ju) * NVn;
-  };
-  const T* __restrict__ fin = a.fin + static_cast<size_t>(iv0) * N + jl;
+  const unsigned vo = act ? lane * S : kOffOOB;
+  const unsigned NVn = static_cast<unsigned>(a.Nv) * N;
+  const unsigned NUn = static_cast<unsigned>(a.Nu) * N;
+  const size_t xstride = static_cast<size_t>(N) * NUn * NVn;   // values per x element
+  const unsigned xbytes = static_cast<unsigned>(xstride * S);
+  const unsigned c0 = iv0 * N;                                  // first v node of the chunk
+  // byte offset of (row (jx, iu', ju), chunk start) inside one x element
+  auto soff = [&](int jx, int iue, int ju) -> unsigned { return ((jx * NUn + iue * N + ju) * NVn + c0) * S; };
+  const auto rf = xelem_rsrc(a.fin, xstride, ix, xbytes);
+  const auto ru = xelem_rsrc(a.fun, xstride, ix, xbytes);
+  const auto ro = xelem_rsrc(a.out, xstride, ix, xbytes);
 
   T f[N][N];
 #pragma unroll
   for (int jx = 0; jx < N; ++jx)
 #pragma unroll
-    for (int ju = 0; ju < N; ++ju) f[jx][ju] = fin[row(ix, jx, iu, ju)];
+    for (int ju = 0; ju < N; ++ju) f[jx][ju] = B::ld(rf, vo, soff(jx, iu, ju));
 
-  // x faces: the x speed u is uniform per u node, so the upwind side is too.
+  // x faces: the x speed u is uniform per u node, so the upwind side (left
+  // neighbour's last node or right neighbour's first node) is too.
   const int ixl = ix == 0 ? a.Nx - 1 : ix - 1;
   const int ixr = ix == a.Nx - 1 ? 0 : ix + 1;
   T xh[N];
+  {
+    const auto rxl = xelem_rsrc(a.fin, xstride, ixl, xbytes);
+    const auto rxr = xelem_rsrc(a.fin, xstride, ixr, xbytes);
 #pragma unroll
-  for (int ju = 0; ju < N; ++ju) {
-    const T uu = a.ucoord[iu * N + ju];
-    xh[ju] = uu > T(0) ? fin[row(ixl, N - 1, iu, ju)] : (uu < T(0) ? fin[row(ixr, 0, iu, ju)] : T(0));
+    for (int ju = 0; ju < N; ++ju) {
+      const T uu = a.ucoord[iu * N + ju];
+      T h;
+      if (uu > T(0)) h = B::ld(rxl, vo, soff(N - 1, iu, ju));
+      else h = B::ld(rxr, vo, soff(0, iu, ju));
+      xh[ju] = uu == T(0) ? T(0) : h;
+    }
   }
 
-  // u faces: the u speed -E(x) - v B varies per lane (v) and per x node.
-  const T vv = a.vcoord[iv0 * N + jl];
+  // u faces: the u speed -E(x) - v B varies per lane (v) and per x node; the
+  // two candidate rows share one scalar base and differ in the vector offset.
+  const T vv = a.vcoord[c0 + (act ? lane : 0u)];
   const int iul = iu == 0 ? a.Nu - 1 : iu - 1;
   const int iur = iu == a.Nu - 1 ? 0 : iu + 1;
   const bool zl = a.zero_inflow && iu == 0;
   const bool zr = a.zero_inflow && iu == a.Nu - 1;
-  T uh[N], su[N];
-#pragma unroll
-  for (int jx = 0; jx < N; ++jx) {
-    const T au = -static_cast<T>(a.E[ix * N + jx]) - vv * a.wc;
-    su[jx] = a.Ju * au;
-    const T* p = au > T(0) ? fin + row(ix, jx, iul, N - 1) : fin + row(ix, jx, iur, 0);
-    const T val = *p;
+  auto uspeed = [&](int jx) -> T { return -static_cast<T>(a.E[ix * N + jx]) - vv * a.wc; };
+  auto uface = [&](int jx) -> T {
+    const T au = uspeed(jx);
+    const unsigned oL = soff(jx, iul, N - 1), oR = soff(jx, iur, 0);
+    const unsigned ob = min(oL, oR);
+    const unsigned vu = act ? lane * S + ((au > T(0) ? oL : oR) - ob) : kOffOOB;
+    const T val = B::ld(rf, vu, ob);
     const bool zero = (au == T(0)) || (au > T(0) ? zl : zr);
-    uh[jx] = zero ? T(0) : val;
-  }
+    return zero ? T(0) : val;
+  };
 
   // v faces: the v speed u B is uniform per u node; one halo value per
   // (x node, u node) row, from the upwind neighbouring v element.
-  {
-    const T* base = a.fin;
-    for (int h = lane; h < N * N; h += kWave) {
-      const int jx = h / N, ju = h % N;
-      const T av = a.ucoord[iu * N + ju] * a.wc;
-      size_t jv;
-      bool outside;
-      if (av > T(0)) {
-        outside = iv0 == 0;
-        jv = outside ? NVn - 1 : static_cast<size_t>(iv0) * N - 1;
-      } else {
-        const int e = iv0 + tva;
-        outside = e == a.Nv;
-        jv = outside ? 0 : static_cast<size_t>(e) * N;
-      }
-      const T val = base[row(ix, jx, iu, ju) + jv];
-      hbuf[h] = (av == T(0) || (outside && a.zero_inflow)) ? T(0) : val;
+  for (unsigned h = lane; h < N * N; h += kWave) {
+    const int jx = h / N, ju = h % N;
+    const T av = a.ucoord[iu * N + ju] * a.wc;
+    unsigned jv;
+    bool outside;
+    if (av > T(0)) {
+      outside = iv0 == 0;
+      jv = outside ? NVn - 1 : c0 - 1;
+    } else {
+      const int e = iv0 + tva;
+      outside = e == a.Nv;
+      jv = outside ? 0u : static_cast<unsigned>(e) * N;
     }
+    const T val = B::ld(rf, ((jx * NUn + iu * N + ju) * NVn + jv) * S, 0u);
+    hbuf[h] = (av == T(0) || (outside && a.zero_inflow)) ? T(0) : val;
   }
 
-  T acc[N][N];
-  // x axis: contract over the x node index (column ju of the slab).
-#pragma unroll
-  for (int ju = 0; ju < N; ++ju) {
-    const T uu = a.ucoord[iu * N + ju];
-    const T fL = uu > T(0) ? xh[ju] : f[0][ju];
-    const T fR = uu > T(0) ? f[N - 1][ju] : xh[ju];
-    T r[N];
-    contract<T, N, false>(op, [&](int k) { return f[k][ju]; }, fL, fR, a.Jx * uu, r);
-#pragma unroll
-    for (int i = 0; i < N; ++i) acc[i][ju] = r[i];
-  }
-  // u axis: contract over the u node index (row jx of the slab).
-#pragma unroll
-  for (int jx = 0; jx < N; ++jx) {
-    const bool pos = su[jx] > T(0);
-    const T fL = pos ? uh[jx] : f[jx][0];
-    const T fR = pos ? f[jx][N - 1] : uh[jx];
-    contract<T, N, true>(op, [&](int k) { return f[jx][k]; }, fL, fR, su[jx], acc[jx]);
-  }
-  // v axis through LDS, one x node at a time.  Pencil owner: row pr (= u
-  // node), element pv of the chunk.
+  // v-axis pencil owner: lane = pv*N + pr (row pr = u node, element pv of the
+  // chunk); idle lanes work on the scratch row N.
   const bool pact = lane < N * tva;
-  const int pr = pact ? lane / tva : 0;
-  const int pv = pact ? lane % tva : 0;
-  const T sv = a.Jv * a.ucoord[iu * N + pr] * a.wc;
+  const int pr = pact ? lane % N : N;
+  const int pv = pact ? lane / N : 0;
+  const T sv = pact ? a.Jv * a.ucoord[iu * N + pr] * a.wc : T(0);
   const int hside = (lane < N && a.ucoord[iu * N + lane] * a.wc > T(0)) ? 0 : nact + 1;
-#pragma unroll
-  for (int jx = 0; jx < N; ++jx) {
-    __syncthreads();
-    if (act) {
-#pragma unroll
-      for (int ju = 0; ju < N; ++ju) lds[ju * ROW + 1 + lane] = f[jx][ju];
-    }
-    if (lane < N) lds[lane * ROW + hside] = hbuf[jx * N + lane];
-    __syncthreads();
-    T g[N + 2];
-#pragma unroll
-    for (int k = 0; k < N + 2; ++k) g[k] = lds[pr * ROW + pv * N + k];
-    const T fL = sv > T(0) ? g[0] : g[1];
-    const T fR = sv > T(0) ? g[N] : g[N + 1];
-    T r[N];
-    contract<T, N, false>(op, [&](int k) { return g[k + 1]; }, fL, fR, sv, r);
-    __syncthreads();
-    if (pact) {
-#pragma unroll
-      for (int i = 0; i < N; ++i) lds[pr * ROW + pv * N + 1 + i] = r[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ju = 0; ju < N; ++ju) acc[jx][ju] += lds[ju * ROW + 1 + lane];
-  }
+  const double wvl = act ? a.wv[c0 + lane] * a.hu : 0.0;    // v weight times du/2
+  const int ntiles = a.Nu * a.nvchunks;
 
-  // epilogue: stage combination, store, FP64 density partials.
-  const T* __restrict__ fun = a.fun + static_cast<size_t>(iv0) * N + jl;
-  T* __restrict__ out = a.out + static_cast<size_t>(iv0) * N + jl;
-  const bool use_un = a.c_un != T(0);
+  // rows of u^n and of the u face are fetched one row ahead of their use
+  T unr[N];
+  if (UN) {
 #pragma unroll
-  for (int jx = 0; jx < N; ++jx)
+    for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld(ru, vo, soff(0, iu, ju));
+  }
+  T uh = uface(0);
+
+  // LDS: lin holds the current x node's row of f (input of the v pencils),
+  // lout[2] the v-axis results of the last two rows (double buffered).
+  T* const lin = lds;
+  T* const lout0 = lds + (N + 1) * ROW;
+  T* const lout1 = lds + 2 * (N + 1) * ROW;
+  auto put_row = [&](int jx) {
+#pragma unroll
+    for (int ju = 0; ju < N; ++ju) lin[ju * ROW + 1 + lane] = f[jx][ju];
+    if (lane < N) lin[lane * ROW + hside] = hbuf[jx * N + lane];
+  };
+  // stage combination, store and FP64 density partial of a finished row
+  auto finish_row = [&](int jx, const T* acc, const T* lo) {
+    T vrow[N];
 #pragma unroll
     for (int ju = 0; ju < N; ++ju) {
-      T v = fmadd(a.c_dt, acc[jx][ju], a.c_in * f[jx][ju]);
-      if (use_un) v = fmadd(a.c_un, fun[row(ix, jx, iu, ju)], v);
-      f[jx][ju] = v;
-      if (act) out[row(ix, jx, iu, ju)] = v;
+      const T rhs = acc[ju] + lo[ju * ROW + 1 + lane];
+      T v = fmadd(a.c_dt, rhs, a.c_in * f[jx][ju]);
+      if (UN) v = fmadd(a.c_un, unr[ju], v);
+      vrow[ju] = v;
     }
-  if (a.partials) {
-    const double wvl = act ? a.wv[iv0 * N + jl] : 0.0;
-    const int ntiles = a.Nu * a.nvchunks;
+    // next u^n row issued before this row's stores (loads and stores share one
+    // in-order completion counter)
+    if (UN && jx + 1 < N) {
 #pragma unroll
-    for (int jx = 0; jx < N; ++jx) {
-      double s = 0.0;
-#pragma unroll
-      for (int ju = 0; ju < N; ++ju) s = __builtin_fma(a.wu[iu * N + ju], static_cast<double>(f[jx][ju]), s);
-      // lanes past the ragged end of the chunk hold garbage: select, never multiply by 0
-      s = wave_sum(act ? s * wvl : 0.0);
-      if (lane == 0) a.partials[static_cast<size_t>(ix * N + jx) * ntiles + iu * a.nvchunks + vc] = s;
+      for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld(ru, vo, soff(jx + 1, iu, ju));
     }
+    // density partial: (du/2) sum_ju w_ju v, reference weights as literals
+    double sum = 0.0;
+#pragma unroll
+    for (int ju = 0; ju < N; ++ju) {
+      B::st(vrow[ju], ro, vo, soff(jx, iu, ju));
+      sum = __builtin_fma(K.w[ju], static_cast<double>(vrow[ju]), sum);
+    }
+    if (a.partials) {
+      // idle lanes: select, never multiply by a zero weight
+      sum = wave_sum(act ? sum * wvl : 0.0);
+      if (lane == 0) a.partials[static_cast<size_t>(ix * N + jx) * ntiles + iu * a.nvchunks + vc] = sum;
+    }
+  };
+
+  // Software-pipelined loop over the x nodes (rows of the slab).  Row jx:
+  // its f row goes to LDS, the register-only x and u parts run while the LDS
+  // write and the pencil reads are in flight, the v result goes to lout, and
+  // the row is finished during the next iteration, after that row's register
+  // work has covered the LDS latency.  LDS accesses of one wave execute in
+  // order, so only compiler ordering is needed.
+  put_row(0);
+  T accp[N];     // x+u parts of the previous row, finished one iteration late
+#pragma unroll
+  for (int jx = 0; jx < N; ++jx) {
+    T acc[N];
+    // x axis: acc_ju = Jx u_ju (sum_k Ups[jx][k] f[k][ju] + Xl[jx] fL - Xr[jx] fR)
+#pragma unroll
+    for (int ju = 0; ju < N; ++ju) {
+      const T uu = a.ucoord[iu * N + ju];
+      const T fL = uu > T(0) ? xh[ju] : f[0][ju];
+      const T fR = uu > T(0) ? f[N - 1][ju] : xh[ju];
+      T t = static_cast<T>(K.xl[jx]) * fL - static_cast<T>(K.xr[jx]) * fR;
+#pragma unroll
+      for (int k = 0; k < N; ++k) t = fmadd(static_cast<T>(K.ups[jx][k]), f[k][ju], t);
+      acc[ju] = (a.Jx * uu) * t;
+    }
+    wave_lds_order();
+    T g[N + 2];
+#pragma unroll
+    for (int k = 0; k < N + 2; ++k) g[k] = lin[pr * ROW + pv * N + k];
+    // u axis along the row (covers the pencil read latency)
+    {
+      const T su = a.Ju * uspeed(jx);
+      const bool pos = su > T(0);
+      const T fL = pos ? uh : f[jx][0];
+      const T fR = pos ? f[jx][N - 1] : uh;
+      contract<T, N, true>([&](int k) { return f[jx][k]; }, fL, fR, su, acc);
+    }
+    if (jx + 1 < N) uh = uface(jx + 1);
+    // v axis on the pencil
+    {
+      const T fL = sv > T(0) ? g[0] : g[1];
+      const T fR = sv > T(0) ? g[N] : g[N + 1];
+      T r[N];
+      contract<T, N, false>([&](int k) { return g[k + 1]; }, fL, fR, sv, r);
+      T* lo = (jx & 1) ? lout1 : lout0;
+      wave_lds_order();
+#pragma unroll
+      for (int i = 0; i < N; ++i) lo[pr * ROW + pv * N + 1 + i] = r[i];
+    }
+    if (jx + 1 < N) put_row(jx + 1);
+    wave_lds_order();
+    if (jx > 0) finish_row(jx - 1, accp, (jx & 1) ? lout0 : lout1);
+#pragma unroll
+    for (int i = 0; i < N; ++i) accp[i] = acc[i];
   }
+  wave_lds_order();
+  finish_row(N - 1, accp, ((N - 1) & 1) ? lout1 : lout0);
 }
 
 // -------------------------------------------------------------------------
 // 1D1V stage kernel.  state [Nx, N, Nv, N]; x speed v, v speed -E(x).
 // -------------------------------------------------------------------------
-template <typename T, int N>
-__global__ void __launch_bounds__(kWave) stage1v_kernel(StageArgs<T> a, Ops<T> op) {
+template <typename T, int N, bool UN>
+__global__ void __launch_bounds__(kWave) stage1v_kernel(StageArgs<T> a) {
+  using B = Buf<T>;
+  constexpr unsigned S = sizeof(T);
   constexpr int TV = kWave / N;
-  constexpr int ROW = kWave + 2;   // >= TV*N + 2; lane+1 stays inside a row
-  __shared__ T lds[N * ROW];
+  constexpr int ROW = lds_row<N>();
+  __shared__ T lds[(N + 1) * ROW];
 
-  const int lane = threadIdx.x;
+  const unsigned lane = threadIdx.x;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int vc = bid % a.nvchunks;
   const int ix = bid / a.nvchunks;
   const int iv0 = vc * TV;
   const int tva = min(TV, a.Nv - iv0);
-  const int nact = tva * N;
+  const unsigned nact = tva * N;
   const bool act = lane < nact;
-  const int jl = act ? lane : 0;
-  const size_t NVn = static_cast<size_t>(a.Nv) * N;
-  auto row = [&](int ixe, int jx) -> size_t { return (static_cast<size_t>(ixe) * N + jx) * NVn; };
-  const T* __restrict__ fin = a.fin + static_cast<size_t>(iv0) * N + jl;
+  const unsigned vo = act ? lane * S : kOffOOB;
+  const unsigned NVn = static_cast<unsigned>(a.Nv) * N;
+  const size_t xstride = static_cast<size_t>(N) * NVn;
+  const unsigned xbytes = static_cast<unsigned>(xstride * S);
+  const unsigned c0 = iv0 * N;
+  auto soff = [&](int jx) -> unsigned { return (jx * NVn + c0) * S; };
+  const auto rf = xelem_rsrc(a.fin, xstride, ix, xbytes);
 
   T f[N];
 #pragma unroll
-  for (int jx = 0; jx < N; ++jx) f[jx] = fin[row(ix, jx)];
-  const T vv = a.vcoord[iv0 * N + jl];
+  for (int jx = 0; jx < N; ++jx) f[jx] = B::ld(rf, vo, soff(jx));
+  const T vv = a.vcoord[c0 + (act ? lane : 0u)];
   const int ixl = ix == 0 ? a.Nx - 1 : ix - 1;
   const int ixr = ix == a.Nx - 1 ? 0 : ix + 1;
-  const T xh = vv > T(0) ? fin[row(ixl, N - 1)] : (vv < T(0) ? fin[row(ixr, 0)] : T(0));
+  // x faces: the x speed v varies per lane; both candidate rows are coalesced.
+  const T hl = B::ld(xelem_rsrc(a.fin, xstride, ixl, xbytes), vo, soff(N - 1));
+  const T hr = B::ld(xelem_rsrc(a.fin, xstride, ixr, xbytes), vo, soff(0));
+  const T xh = vv > T(0) ? hl : (vv < T(0) ? hr : T(0));
 
   T acc[N];
   {
     const T fL = vv > T(0) ? xh : f[0];
     const T fR = vv > T(0) ? f[N - 1] : xh;
-    contract<T, N, false>(op, [&](int k) { return f[k]; }, fL, fR, a.Jx * vv, acc);
+    contract<T, N, false>([&](int k) { return f[k]; }, fL, fR, a.Jx * vv, acc);
   }
   // v faces, one per x node row, from the side selected by the sign of -E.
   T hval = T(0);
   int hside = 0;
   if (lane < N) {
     const T av = -static_cast<T>(a.E[ix * N + lane]);
-    size_t jv;
+    unsigned jv;
     bool outside;
     if (av > T(0)) {
       outside = iv0 == 0;
-      jv = outside ? NVn - 1 : static_cast<size_t>(iv0) * N - 1;
+      jv = outside ? NVn - 1 : c0 - 1;
       hside = 0;
     } else {
       const int e = iv0 + tva;
       outside = e == a.Nv;
-      jv = outside ? 0 : static_cast<size_t>(e) * N;
+      jv = outside ? 0u : static_cast<unsigned>(e) * N;
       hside = nact + 1;
     }
-    const T val = a.fin[row(ix, lane) + jv];
+    const T val = B::ld(rf, (lane * NVn + jv) * S, 0u);
     hval = (av == T(0) || (outside && a.zero_inflow)) ? T(0) : val;
   }
-  if (act) {
 #pragma unroll
-    for (int jx = 0; jx < N; ++jx) lds[jx * ROW + 1 + lane] = f[jx];
-  }
+  for (int jx = 0; jx < N; ++jx) lds[jx * ROW + 1 + lane] = f[jx];
   if (lane < N) lds[lane * ROW + hside] = hval;
-  __syncthreads();
+  wave_lds_order();
   const bool pact = lane < N * tva;
-  const int pr = pact ? lane / tva : 0;
-  const int pv = pact ? lane % tva : 0;
-  const T sv = -a.Jv * static_cast<T>(a.E[ix * N + pr]);
-  T g[N + 2];
-#pragma unroll
-  for (int k = 0; k < N + 2; ++k) g[k] = lds[pr * ROW + pv * N + k];
+  const int pr = pact ? lane % N : N;
+  const int pv = pact ? lane / N : 0;
+  const T sv = pact ? -a.Jv * static_cast<T>(a.E[ix * N + pr]) : T(0);
   {
+    T g[N + 2];
+#pragma unroll
+    for (int k = 0; k < N + 2; ++k) g[k] = lds[pr * ROW + pv * N + k];
     const T fL = sv > T(0) ? g[0] : g[1];
     const T fR = sv > T(0) ? g[N] : g[N + 1];
     T r[N];
-    contract<T, N, false>(op, [&](int k) { return g[k + 1]; }, fL, fR, sv, r);
-    __syncthreads();
-    if (pact) {
+    contract<T, N, false>([&](int k) { return g[k + 1]; }, fL, fR, sv, r);
+    wave_lds_order();
 #pragma unroll
-      for (int i = 0; i < N; ++i) lds[pr * ROW + pv * N + 1 + i] = r[i];
-    }
+    for (int i = 0; i < N; ++i) lds[pr * ROW + pv * N + 1 + i] = r[i];
   }
-  __syncthreads();
-#pragma unroll
-  for (int jx = 0; jx < N; ++jx) acc[jx] += lds[jx * ROW + 1 + lane];
-
-  const T* __restrict__ fun = a.fun + static_cast<size_t>(iv0) * N + jl;
-  T* __restrict__ out = a.out + static_cast<size_t>(iv0) * N + jl;
-  const bool use_un = a.c_un != T(0);
+  wave_lds_order();
+  const auto ru = xelem_rsrc(a.fun, xstride, ix, xbytes);
+  const auto ro = xelem_rsrc(a.out, xstride, ix, xbytes);
+  const double wvl = act ? a.wv[c0 + lane] : 0.0;
 #pragma unroll
   for (int jx = 0; jx < N; ++jx) {
-    T v = fmadd(a.c_dt, acc[jx], a.c_in * f[jx]);
-    if (use_un) v = fmadd(a.c_un, fun[row(ix, jx)], v);
-    f[jx] = v;
-    if (act) out[row(ix, jx)] = v;
-  }
-  if (a.partials) {
-    const double wvl = act ? a.wv[iv0 * N + jl] : 0.0;
-#pragma unroll
-    for (int jx = 0; jx < N; ++jx) {
-      const double s = wave_sum(act ? wvl * static_cast<double>(f[jx]) : 0.0);
+    const T rhs = acc[jx] + lds[jx * ROW + 1 + lane];
+    T v = fmadd(a.c_dt, rhs, a.c_in * f[jx]);
+    if (UN) v = fmadd(a.c_un, B::ld(ru, vo, soff(jx)), v);
+    B::st(v, ro, vo, soff(jx));
+    if (a.partials) {
+      const double s = wave_sum(act ? wvl * static_cast<double>(v) : 0.0);
       if (lane == 0) a.partials[static_cast<size_t>(ix * N + jx) * a.nvchunks + vc] = s;
     }
   }
@@ -408,98 +568,151 @@ __global__ void __launch_bounds__(kWave) moments_kernel(StageArgs<T> a, double* 
 }
 
 // -------------------------------------------------------------------------
-// Field solve (FP64).  Stage A: one block per x element reduces the density
-// partials in a fixed order, forms that element's Fourier partial sums
-// sum_j T_p^{mj} (n_mj - 1) and its mass.  Stage B: one block sums the
-// partials over elements in order, synthesises E at every x node
-// (eq. electric_sol) and records mass, field energy and max|E|.
+// Field solve (FP64), two launches per stage (a kernel boundary orders the
+// hand-over; a device-scope fence would write back and invalidate L2).
+//   fieldA: block ix (one wave) reduces the density partials of its x element
+//           in a fixed order and forms its Fourier sums
+//           sum_j T_p^{mj} (n_mj - 1)  (eq. spectral_transform) and its mass.
+//   fieldB: one block sums those in element order, synthesises E at every x
+//           node, E_mj = sum_{p=1..pmax} 2 Re((i / k_p) c_p e^{i k_p x_mj})
+//           (eq. electric_sol), with e^{i k_p x} from the recurrence
+//           z_p = z_{p-1} z_1, and writes the diagnostics record.
+// No float atomics: results are bitwise reproducible.
 // -------------------------------------------------------------------------
-constexpr int kFieldThreads = 256;
+constexpr int kFieldB = 256;
 
-__global__ void __launch_bounds__(kFieldThreads) fieldA_kernel(FieldArgs a) {
-  __shared__ double red[kFieldThreads];
+constexpr int kFieldA = 256;
+
+__global__ void __launch_bounds__(kFieldA) fieldA_kernel(FieldArgs a) {
   __shared__ double dens[kMaxN];
-  const int ix = blockIdx.x, tid = threadIdx.x, n = a.n;
-  for (int jx = 0; jx < n; ++jx) {
-    const double* p = a.partials + static_cast<size_t>(ix * n + jx) * a.ntiles;
-    double s = 0.0;
-    for (int t = tid; t < a.ntiles; t += kFieldThreads) s += p[t];
-    red[tid] = s;
-    __syncthreads();
-    for (int w = kFieldThreads / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
+  __shared__ double red[kFieldA / kWave][kMaxN];
+  const int ix = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave, n = a.n;
+  // thread-strided partial sums for all x nodes at once (n loads in flight),
+  // wave sums, then the waves' results added in order
+  double s[kMaxN];
+#pragma unroll
+  for (int j = 0; j < kMaxN; ++j) s[j] = 0.0;
+  const double* base = a.partials + static_cast<size_t>(ix * n) * a.ntiles;
+  for (int t = tid; t < a.ntiles; t += kFieldA) {
+#pragma unroll
+    for (int j = 0; j < kMaxN; ++j)
+      if (j < n) s[j] += base[static_cast<size_t>(j) * a.ntiles + t];
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxN; ++j) {
+    if (j < n) {
+      const double d = wave_sum(s[j]);
+      if (lane == 0) red[wid][j] = d;
     }
-    if (tid == 0) dens[jx] = red[0];
-    __syncthreads();
   }
-  if (tid < n) a.dens[ix * n + tid] = dens[tid];
-  if (tid == 0) {
-    double m = 0.0;
-    for (int j = 0; j < n; ++j) m += a.wx[ix * n + j] * dens[j];
-    a.mpart[ix] = m;
+  __syncthreads();
+  if (tid < n) {
+    double d = 0.0;
+    for (int w = 0; w < kFieldA / kWave; ++w) d += red[w][tid];
+    dens[tid] = d;
+    a.dens[ix * n + tid] = d;
   }
-  const int nodes = a.Nx * n;
-  for (int p = tid; p < a.pmax; p += kFieldThreads) {
+  __syncthreads();
+  for (int p = tid; p < a.pmax; p += kFieldA) {
     double cr = 0.0, ci = 0.0;
     for (int j = 0; j < n; ++j) {
-      const double* t = a.T + 2 * (static_cast<size_t>(p) * nodes + ix * n + j);
-      const double s = dens[j] - 1.0;
-      cr += t[0] * s;
-      ci += t[1] * s;
+      const double* t = a.T + 2 * (static_cast<size_t>(ix * n + j) * a.pmax + p);
+      const double sj = dens[j] - 1.0;
+      cr = __builtin_fma(t[0], sj, cr);
+      ci = __builtin_fma(t[1], sj, ci);
     }
     a.cpart[2 * (static_cast<size_t>(ix) * a.pmax + p) + 0] = cr;
     a.cpart[2 * (static_cast<size_t>(ix) * a.pmax + p) + 1] = ci;
   }
+  if (tid == 0) {
+    double m = 0.0;
+    for (int j = 0; j < n; ++j) m = __builtin_fma(a.wx[ix * n + j], dens[j], m);
+    a.mpart[ix] = m;
+  }
 }
 
-__global__ void __launch_bounds__(kFieldThreads) fieldB_kernel(FieldArgs a) {
-  extern __shared__ double sh[];          // 2 * pmax coefficients
-  __shared__ double red[kFieldThreads];
-  __shared__ double redm[kFieldThreads];
-  const int tid = threadIdx.x, n = a.n, nodes = a.Nx * a.n;
-  for (int p = tid; p < a.pmax; p += kFieldThreads) {
+__global__ void __launch_bounds__(kFieldB) fieldB_kernel(FieldArgs a) {
+  extern __shared__ double csh[];          // 2 * pmax coefficients
+  __shared__ double red[2][kFieldB];
+  const int tid = threadIdx.x;
+  // c_p = sum over elements of the element partials: kFieldB/4 groups... each
+  // thread sums a quarter of the elements for one p (8 loads in flight), the
+  // quarters are then added in order.
+  constexpr int G = 4;
+  for (int base = 0; base < a.pmax; base += kFieldB / G) {
+    const int p = base + tid % (kFieldB / G);
+    const int g = tid / (kFieldB / G);
     double cr = 0.0, ci = 0.0;
-    for (int ix = 0; ix < a.Nx; ++ix) {
-      cr += a.cpart[2 * (static_cast<size_t>(ix) * a.pmax + p) + 0];
-      ci += a.cpart[2 * (static_cast<size_t>(ix) * a.pmax + p) + 1];
+    if (p < a.pmax) {
+      const int e0 = g * a.Nx / G, e1 = (g + 1) * a.Nx / G;
+#pragma unroll 8
+      for (int e = e0; e < e1; ++e) {
+        cr += a.cpart[2 * (static_cast<size_t>(e) * a.pmax + p) + 0];
+        ci += a.cpart[2 * (static_cast<size_t>(e) * a.pmax + p) + 1];
+      }
     }
-    sh[2 * p] = cr;
-    sh[2 * p + 1] = ci;
-    if (a.coeffs) {
-      a.coeffs[2 * p] = cr;
-      a.coeffs[2 * p + 1] = ci;
+    red[0][tid] = cr;
+    red[1][tid] = ci;
+    __syncthreads();
+    if (tid < kFieldB / G && base + tid < a.pmax) {
+      double r = 0.0, i = 0.0;
+      for (int q = 0; q < G; ++q) {
+        r += red[0][q * (kFieldB / G) + tid];
+        i += red[1][q * (kFieldB / G) + tid];
+      }
+      csh[2 * (base + tid)] = r;
+      csh[2 * (base + tid) + 1] = i;
+      if (a.coeffs) {
+        a.coeffs[2 * (base + tid)] = r;
+        a.coeffs[2 * (base + tid) + 1] = i;
+      }
     }
+    __syncthreads();
   }
+  // mass: element partials reduced by a fixed tree
+  double mp = 0.0;
+  for (int e = tid; e < a.Nx; e += kFieldB) mp += a.mpart[e];
+  red[0][tid] = mp;
   __syncthreads();
+  for (int w = kFieldB / 2; w > 0; w >>= 1) {
+    if (tid < w) red[0][tid] += red[0][tid + w];
+    __syncthreads();
+  }
+  const double mass = red[0][0];
+  __syncthreads();
+  const int nodes = a.Nx * a.n;
   double fe = 0.0, mx = 0.0;
-  for (int node = tid; node < nodes; node += kFieldThreads) {
-    double e = 0.0;
+  for (int node = tid; node < nodes; node += kFieldB) {
+    const double z1r = a.z1[2 * node], z1i = a.z1[2 * node + 1];
+    double zr = z1r, zi = z1i, e = 0.0;
     for (int p = 0; p < a.pmax; ++p) {
-      const double* g = a.G + 2 * (static_cast<size_t>(p) * nodes + node);
-      e += 2.0 * (sh[2 * p] * g[0] - sh[2 * p + 1] * g[1]);
+      // 2 Re((i / k) c z) = -(2 / k) Im(c z),  k = (p + 1) k_1
+      const double cr = csh[2 * p], ci = csh[2 * p + 1];
+      e = __builtin_fma(-2.0 / ((p + 1) * a.k1), __builtin_fma(cr, zi, ci * zr), e);
+      const double t = zr * z1r - zi * z1i;
+      zi = __builtin_fma(zr, z1i, zi * z1r);
+      zr = t;
     }
     a.E[node] = e;
-    fe += a.wx[node] * e * e;
+    fe = __builtin_fma(a.wx[node] * e, e, fe);
     mx = fmax(mx, fabs(e));
   }
-  red[tid] = fe;
-  redm[tid] = mx;
+  red[0][tid] = fe;
+  red[1][tid] = mx;
   __syncthreads();
-  for (int w = kFieldThreads / 2; w > 0; w >>= 1) {
+  for (int w = kFieldB / 2; w > 0; w >>= 1) {
     if (tid < w) {
-      red[tid] += red[tid + w];
-      redm[tid] = fmax(redm[tid], redm[tid + w]);
+      red[0][tid] += red[0][tid + w];
+      red[1][tid] = fmax(red[1][tid], red[1][tid + w]);
     }
     __syncthreads();
   }
   if (tid == 0) {
-    double m = 0.0;
-    for (int ix = 0; ix < a.Nx; ++ix) m += a.mpart[ix];
-    const double fen = 0.5 * red[0];
-    const bool fin = isfinite(m) && isfinite(fen) && isfinite(redm[0]);
+    const double m = mass;
+    const double fen = 0.5 * red[0][0];
+    const bool fin = isfinite(m) && isfinite(fen) && isfinite(red[1][0]);
     const int k = (a.record && a.ring) ? *a.counter : -1;
-    double rec[8] = {0.0, m, fen, 0.0, 0.0, redm[0], fin ? 1.0 : 0.0, static_cast<double>(k)};
+    double rec[8] = {0.0, m, fen, 0.0, 0.0, red[1][0], fin ? 1.0 : 0.0, static_cast<double>(k)};
     for (int q = 0; q < 8; ++q) a.last[q] = rec[q];
     if (k >= 0) {
       double* r = a.ring + 8 * (k % kRing);
@@ -507,8 +720,9 @@ __global__ void __launch_bounds__(kFieldThreads) fieldB_kernel(FieldArgs a) {
       *a.counter = k + 1;
     }
   }
-  (void)n;
 }
+
+constexpr int kFieldThreads = 256;
 
 __global__ void moments_reduce_kernel(const double* mom, int ntiles, double* ring, const int* counter) {
   __shared__ double red[3][kFieldThreads];
@@ -553,18 +767,21 @@ __global__ void reset_counter_kernel(int* c) { *c = 0; }
 // -------------------------------------------------------------------------
 template <typename T, int N>
 static hipError_t stage_t(int nv, const void* args, int ntiles, hipStream_t s) {
-  const StageArgs<T>& a = static_cast<const StagePack<T>*>(args)->a;
-  const Ops<T>& op = static_cast<const StagePack<T>*>(args)->op;
-  if (nv == 2)
-    hipLaunchKernelGGL((stage2v_kernel<T, N>), dim3(ntiles), dim3(kWave), 0, s, a, op);
-  else
-    hipLaunchKernelGGL((stage1v_kernel<T, N>), dim3(ntiles), dim3(kWave), 0, s, a, op);
+  const StageArgs<T>& a = *static_cast<const StageArgs<T>*>(args);
+  const bool un = a.c_un != T(0);
+  if (nv == 2) {
+    if (un) hipLaunchKernelGGL((stage2v_kernel<T, N, true>), dim3(ntiles), dim3(kWave), 0, s, a);
+    else hipLaunchKernelGGL((stage2v_kernel<T, N, false>), dim3(ntiles), dim3(kWave), 0, s, a);
+  } else {
+    if (un) hipLaunchKernelGGL((stage1v_kernel<T, N, true>), dim3(ntiles), dim3(kWave), 0, s, a);
+    else hipLaunchKernelGGL((stage1v_kernel<T, N, false>), dim3(ntiles), dim3(kWave), 0, s, a);
+  }
   return hipGetLastError();
 }
 
 template <typename T, int N>
 static hipError_t density_t(int nv, const void* args, int ntiles, hipStream_t s) {
-  const StageArgs<T>& a = static_cast<const StagePack<T>*>(args)->a;
+  const StageArgs<T>& a = *static_cast<const StageArgs<T>*>(args);
   if (nv == 2)
     hipLaunchKernelGGL((density_kernel<T, N, 2>), dim3(ntiles), dim3(kWave), 0, s, a);
   else
@@ -574,7 +791,7 @@ static hipError_t density_t(int nv, const void* args, int ntiles, hipStream_t s)
 
 template <typename T, int N>
 static hipError_t moments_t(int nv, const void* args, double* mom, int ntiles, hipStream_t s) {
-  const StageArgs<T>& a = static_cast<const StagePack<T>*>(args)->a;
+  const StageArgs<T>& a = *static_cast<const StageArgs<T>*>(args);
   if (nv == 2)
     hipLaunchKernelGGL((moments_kernel<T, N, 2>), dim3(ntiles), dim3(kWave), 0, s, a, mom);
   else
@@ -611,10 +828,10 @@ hipError_t launch_moments(int nv, int n, bool f64, const void* args, double* mom
 }
 
 hipError_t launch_field(const FieldArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(fieldA_kernel, dim3(a.Nx), dim3(kFieldThreads), 0, s, a);
+  hipLaunchKernelGGL(fieldA_kernel, dim3(a.Nx), dim3(kFieldA), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fieldB_kernel, dim3(1), dim3(kFieldThreads), 2 * a.pmax * sizeof(double), s, a);
+  hipLaunchKernelGGL(fieldB_kernel, dim3(1), dim3(kFieldB), 2 * a.pmax * sizeof(double), s, a);
   return hipGetLastError();
 }
 

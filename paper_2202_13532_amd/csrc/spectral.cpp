@@ -1,5 +1,5 @@
 // FP64 host construction of the LGL -> Fourier connection tensor (Sec. 5.3,
-// eq. spectral_transform) and of the field-synthesis table (eq. electric_sol).
+// eq. spectral_transform).
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -73,22 +73,6 @@ std::vector<cd> connection_tensor(const Basis& b, int nelem, double lo, double h
       const cd ph = (dx / L) * std::polar(1.0, -kp * xbar);
       for (int j = 0; j < n; ++j) out[(static_cast<size_t>(p - 1) * nelem + m) * n + j] = ph * tau[j];
     }
-  }
-  return out;
-}
-
-std::vector<cd> field_synthesis(const Basis& b, int nelem, double lo, double hi, int pmax) {
-  const int n = b.n;
-  const double L = hi - lo, dx = L / nelem;
-  std::vector<cd> out(static_cast<size_t>(pmax) * nelem * n);
-  for (int p = 1; p <= pmax; ++p) {
-    const double kp = 2.0 * M_PI * p / L;
-    for (int m = 0; m < nelem; ++m)
-      for (int j = 0; j < n; ++j) {
-        const double x = lo + (m + 0.5) * dx + b.xi[j] * dx * 0.5;
-        // -(i k_p)^-1 e^{i k_p x} = (i / k_p) e^{i k_p x}
-        out[(static_cast<size_t>(p - 1) * nelem + m) * n + j] = cd(0.0, 1.0 / kp) * std::polar(1.0, kp * x);
-      }
   }
   return out;
 }

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -15,6 +16,9 @@
 #include "../../include/dg.h"
 #include "dg_host.h"
 #include "dg_kernels.h"
+#include "ctx.h"
+
+using dgi::Layout;
 
 namespace {
 
@@ -23,15 +27,6 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 std::mutex g_err_mu;
 std::string g_init_error = "no error";
-
-// Workspace layout derived from a validated configuration.
-struct Layout {
-  size_t esize = 0, dof = 0;
-  int naxes = 0, n = 0, Nx = 0, Nu = 1, Nv = 0, nvchunks = 0, pmax = 0;
-  int ntiles_slab = 0, ntiles = 0;
-  size_t off_B, off_C, off_part, off_mom, off_dens, off_E, off_cpart, off_mpart, off_coef, off_ring,
-      off_last, off_ctr, off_T, off_z1, off_wx, off_wu, off_wv, off_uc, off_vc, off_uc64, off_vc64, total;
-};
 
 const char* validate(const dg_config* c) {
   if (!c) return "cfg is NULL";
@@ -92,31 +87,12 @@ Layout make_layout(const dg_config* c) {
   return L;
 }
 
+const char* check_cfg(const dg_config* cfg, dg_status* st);
+
 }  // namespace
 
-struct dg_ctx {
-  dg_config cfg{};
-  Layout L;
-  dgh::Basis basis;
-  double courant = 0.0;
-  double dx[3] = {0, 0, 0};
-  char* ws = nullptr;
-  hipStream_t user = nullptr;
-  hipStream_t stream = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  double t = 0.0;
-  std::string err = "no error";
-  // cached step graph
-  hipGraphExec_t gexec = nullptr;
-  const void* g_f = nullptr;
-  double g_dt = 0.0;
-  bool g_diag = false;
 
-  template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
-  bool f64() const { return cfg.storage == DG_F64; }
-};
-
-namespace {
+namespace dgi {
 
 dg_status fail(dg_ctx* c, dg_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -238,9 +214,10 @@ dg_status moments(dg_ctx* c, const void* f) {
   return DG_OK;
 }
 
-dg_status field(dg_ctx* c, double* E, double* coeffs, bool record) {
+void fill_field(const dg_ctx* c, dgk::FieldArgs* pa, double* E, double* coeffs, bool record) {
   const Layout& L = c->L;
-  dgk::FieldArgs a{};
+  dgk::FieldArgs& a = *pa;
+  a = dgk::FieldArgs{};
   a.partials = c->at<double>(L.off_part);
   a.ntiles = L.ntiles_slab;
   a.Nx = L.Nx;
@@ -259,6 +236,11 @@ dg_status field(dg_ctx* c, double* E, double* coeffs, bool record) {
   a.last = c->at<double>(L.off_last);
   a.counter = c->at<int>(L.off_ctr);
   a.record = record ? 1 : 0;
+}
+
+dg_status field(dg_ctx* c, double* E, double* coeffs, bool record) {
+  dgk::FieldArgs a;
+  fill_field(c, &a, E, coeffs, record);
   hipError_t e = dgk::launch_field(a, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "field kernel launch");
   return DG_OK;
@@ -340,60 +322,64 @@ void copy_record(const double* r, double t, dg_diag* out) {
   out->step = static_cast<int32_t>(r[7]);
 }
 
-}  // namespace
+}  // namespace dgi
+
+using namespace dgi;
 
 extern "C" {
 
 size_t dg_workspace_bytes(const dg_config* cfg) {
-  if (validate(cfg)) return 0;
-  if (cfg->n > dgk::kMaxN) return 0;
+  dg_status st;
+  if (check_cfg(cfg, &st)) return 0;
   return make_layout(cfg).total;
 }
 
-dg_status dg_init(const dg_config* cfg, void* workspace, size_t workspace_bytes, void* hip_stream, dg_ctx** out) {
-  auto init_fail = [](dg_status s, const std::string& m) {
-    std::lock_guard<std::mutex> lk(g_err_mu);
-    g_init_error = m;
-    return s;
-  };
-  if (!out) return init_fail(DG_ERR_INVALID, "out is NULL");
-  *out = nullptr;
-  if (const char* why = validate(cfg)) return init_fail(DG_ERR_INVALID, why);
-  if (cfg->n > dgk::kMaxN) return init_fail(DG_ERR_UNSUPPORTED, "n above 9 is not built");
-  const Layout L = make_layout(cfg);
-  if (!workspace) return init_fail(DG_ERR_INVALID, "workspace is NULL");
-  if (workspace_bytes < L.total) return init_fail(DG_ERR_OOM, "workspace smaller than dg_workspace_bytes()");
-  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return init_fail(DG_ERR_INVALID, "workspace must be 256-byte aligned");
-  if (L.ntiles <= 0 || static_cast<long long>(L.Nx) * L.ntiles_slab > 0x7fffffffLL)
-    return init_fail(DG_ERR_UNSUPPORTED, "grid too large");
+}  // extern "C"
 
+namespace {
+
+// Build a context on `ws`: FP64 host setup (basis, Courant number, tables)
+// uploaded on `stream`.  If own_stream, the context creates its own
+// non-blocking stream and ordering events (dg_init); otherwise it enqueues on
+// `stream` directly (runs of a batch).  On failure *err holds the reason.
+dg_status make_ctx(const dg_config* cfg, char* ws, hipStream_t user, bool own_stream, dg_ctx** out, std::string* err) {
+  *out = nullptr;
+  const Layout L = make_layout(cfg);
   dg_ctx* c = new (std::nothrow) dg_ctx();
-  if (!c) return init_fail(DG_ERR_INVALID, "host allocation failed");
+  if (!c) { *err = "host allocation failed"; return DG_ERR_INVALID; }
   c->cfg = *cfg;
   c->L = L;
-  c->ws = static_cast<char*>(workspace);
-  c->user = static_cast<hipStream_t>(hip_stream);
+  c->ws = ws;
+  c->user = user;
+  c->owns_stream = own_stream;
   try {
     c->basis = dgh::make_basis(cfg->n);
     c->courant = dgh::courant_number(cfg->n);
   } catch (const std::exception& ex) {
     delete c;
-    return init_fail(DG_ERR_INVALID, std::string("basis setup failed: ") + ex.what());
+    *err = std::string("basis setup failed: ") + ex.what();
+    return DG_ERR_INVALID;
   }
   for (int a = 0; a <= cfg->nv; ++a) c->dx[a] = (cfg->hi[a] - cfg->lo[a]) / cfg->nelem[a];
 
   auto cleanup = [&](hipError_t e, const char* what) {
-    std::string m = std::string(what) + ": " + hipGetErrorString(e);
-    if (c->stream) hipStreamDestroy(c->stream);
-    if (c->ev_in) hipEventDestroy(c->ev_in);
-    if (c->ev_out) hipEventDestroy(c->ev_out);
+    *err = std::string(what) + ": " + hipGetErrorString(e);
+    if (c->owns_stream) {
+      if (c->stream) hipStreamDestroy(c->stream);
+      if (c->ev_in) hipEventDestroy(c->ev_in);
+      if (c->ev_out) hipEventDestroy(c->ev_out);
+    }
     delete c;
-    return init_fail(DG_ERR_DEVICE, m);
+    return DG_ERR_DEVICE;
   };
   hipError_t e;
-  if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) return cleanup(e, "hipStreamCreate");
-  if ((e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming)) != hipSuccess) return cleanup(e, "hipEventCreate");
-  if ((e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming)) != hipSuccess) return cleanup(e, "hipEventCreate");
+  if (own_stream) {
+    if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) return cleanup(e, "hipStreamCreate");
+    if ((e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming)) != hipSuccess) return cleanup(e, "hipEventCreate");
+    if ((e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming)) != hipSuccess) return cleanup(e, "hipEventCreate");
+  } else {
+    c->stream = user;
+  }
 
   // FP64 host tables.
   const int n = cfg->n;
@@ -436,13 +422,53 @@ dg_status dg_init(const dg_config* cfg, void* workspace, size_t workspace_bytes,
   return DG_OK;
 }
 
+// Configuration checks shared by dg_init and the batch.
+const char* check_cfg(const dg_config* cfg, dg_status* st) {
+  *st = DG_ERR_INVALID;
+  if (const char* why = validate(cfg)) return why;
+  *st = DG_ERR_UNSUPPORTED;
+  if (cfg->n > dgk::kMaxN) return "n above 9 is not built";
+  const Layout L = make_layout(cfg);
+  if (L.ntiles <= 0 || static_cast<long long>(L.Nx) * L.ntiles_slab > 0x7fffffffLL) return "grid too large";
+  // one x element must be addressable by a 31-bit buffer offset
+  if (static_cast<double>(L.dof) / L.Nx * L.esize >= 2147483648.0) return "x element larger than 2 GiB";
+  *st = DG_OK;
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+dg_status dg_init(const dg_config* cfg, void* workspace, size_t workspace_bytes, void* hip_stream, dg_ctx** out) {
+  auto init_fail = [](dg_status s, const std::string& m) {
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    g_init_error = m;
+    return s;
+  };
+  if (!out) return init_fail(DG_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  dg_status st;
+  if (const char* why = check_cfg(cfg, &st)) return init_fail(st, why);
+  const Layout L = make_layout(cfg);
+  if (!workspace) return init_fail(DG_ERR_INVALID, "workspace is NULL");
+  if (workspace_bytes < L.total) return init_fail(DG_ERR_OOM, "workspace smaller than dg_workspace_bytes()");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return init_fail(DG_ERR_INVALID, "workspace must be 256-byte aligned");
+  std::string err;
+  st = make_ctx(cfg, static_cast<char*>(workspace), static_cast<hipStream_t>(hip_stream), true, out, &err);
+  if (st != DG_OK) return init_fail(st, err);
+  return DG_OK;
+}
+
 dg_status dg_destroy(dg_ctx* ctx) {
   if (!ctx) return DG_OK;
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
-  hipEventDestroy(ctx->ev_in);
-  hipEventDestroy(ctx->ev_out);
-  hipStreamDestroy(ctx->stream);
+  if (ctx->owns_stream) {
+    hipEventDestroy(ctx->ev_in);
+    hipEventDestroy(ctx->ev_out);
+    hipStreamDestroy(ctx->stream);
+  }
   delete ctx;
   return e == hipSuccess ? DG_OK : DG_ERR_DEVICE;
 }
@@ -486,7 +512,9 @@ double dg_dt_max(const dg_ctx* ctx, double max_abs_E) {
   return ctx->courant / rate;
 }
 
-namespace {
+}  // extern "C"
+
+namespace dgi {
 // Field of the initial state and the CFL check shared by the stepping calls.
 dg_status begin_steps(dg_ctx* ctx, void* f, double dt, int32_t nsteps) {
   if (!f) return fail(ctx, DG_ERR_INVALID, "f is NULL");
@@ -512,7 +540,9 @@ dg_status begin_steps(dg_ctx* ctx, void* f, double dt, int32_t nsteps) {
   }
   return DG_OK;
 }
-}  // namespace
+}  // namespace dgi
+
+extern "C" {
 
 dg_status dg_rk_step(dg_ctx* ctx, void* f, double dt, int32_t nsteps, dg_diag* host_diag) {
   if (!ctx) return DG_ERR_INVALID;
@@ -646,6 +676,449 @@ double dg_courant_number(int32_t n) {
   } catch (...) {
     return 0.0;
   }
+}
+
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: every run keeps its own tables in a sub-workspace; the stage
+// kernels of all runs share one persistent launch per RK stage.
+// ---------------------------------------------------------------------------
+struct dg_batch {
+  int nruns = 0;
+  std::vector<dg_ctx*> runs;
+  std::vector<size_t> run_off;
+  hipStream_t user = nullptr, stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  char* ws = nullptr;
+  // device tables
+  dgk::StageArgs<float>* d_args = nullptr;   // 3 * nruns
+  int* d_kind = nullptr;
+  int2* d_items = nullptr;
+  int* d_xcd = nullptr;
+  dgk::FieldArgs* d_fa = nullptr;             // 3 * nruns (record flag differs)
+  int2* d_xitems = nullptr;
+  int nitems = 0, nxitems = 0, max_pmax = 0;
+  int grid = 0, cus = 0, occ[2] = {0, 0};
+  std::vector<int2> items_cost, items_rr;     // the two work-list orders
+  int order = 0;                              // 0: cost-sorted, 1: run-interleaved
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const void*> g_f;
+  std::vector<double> g_dt;
+  bool g_diag = false;
+  std::string err = "no error";
+};
+
+namespace {
+
+constexpr size_t kBatchTail = 1 << 16;
+
+struct BatchLayout {
+  std::vector<size_t> run_off;
+  size_t args, kind, items, xcd, fa, xitems, total;
+};
+
+BatchLayout batch_layout(const dg_config* cfgs, int nruns) {
+  BatchLayout B;
+  size_t o = 0;
+  int ntiles = 0, nx = 0;
+  for (int r = 0; r < nruns; ++r) {
+    B.run_off.push_back(o);
+    const Layout L = make_layout(&cfgs[r]);
+    o += align_up(L.total);
+    ntiles += L.ntiles;
+    nx += L.Nx;
+  }
+  auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
+  B.args = take(3 * nruns * sizeof(dgk::StageArgs<float>));
+  B.kind = take(nruns * sizeof(int));
+  B.items = take(static_cast<size_t>(ntiles) * sizeof(int2));
+  B.xcd = take(9 * sizeof(int));
+  B.fa = take(3 * nruns * sizeof(dgk::FieldArgs));
+  B.xitems = take(static_cast<size_t>(nx) * sizeof(int2));
+  B.total = o;
+  return B;
+}
+
+dg_status bfail(dg_batch* b, dg_status s, const std::string& m) {
+  if (b) b->err = m;
+  return s;
+}
+
+#define DGB_HIP(b, expr)                                                              \
+  do {                                                                                \
+    hipError_t e__ = (expr);                                                          \
+    if (e__ != hipSuccess) return bfail(b, DG_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e__)); \
+  } while (0)
+
+// Split a work list into 8 contiguous ranges of roughly equal cost.
+std::vector<int> xcd_split(const std::vector<int2>& items, const std::vector<double>& cost_of_run) {
+  double total = 0.0;
+  for (auto& it : items) total += cost_of_run[it.x];
+  std::vector<int> begin(9, static_cast<int>(items.size()));
+  begin[0] = 0;
+  double acc = 0.0;
+  int c = 1;
+  for (size_t i = 0; i < items.size() && c < 8; ++i) {
+    acc += cost_of_run[items[i].x];
+    while (c < 8 && acc >= total * c / 8.0) begin[c++] = static_cast<int>(i + 1);
+  }
+  for (; c < 8; ++c) begin[c] = static_cast<int>(items.size());
+  begin[8] = static_cast<int>(items.size());
+  return begin;
+}
+
+dg_status upload_items(dg_batch* b) {
+  const std::vector<int2>& items = b->order == 0 ? b->items_cost : b->items_rr;
+  std::vector<double> cost(b->nruns);
+  for (int r = 0; r < b->nruns; ++r) {
+    const Layout& L = b->runs[r]->L;
+    cost[r] = static_cast<double>(L.dof) / L.ntiles;
+  }
+  std::vector<int> xcd = xcd_split(items, cost);
+  DGB_HIP(b, hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+  DGB_HIP(b, hipMemcpyAsync(b->d_xcd, xcd.data(), 9 * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  DGB_HIP(b, hipStreamSynchronize(b->stream));
+  return DG_OK;
+}
+
+// Per-stage argument tables for the current states and time steps.
+dg_status upload_args(dg_batch* b, void* const* f, const double* dt) {
+  std::vector<dgk::StageArgs<float>> args(3 * b->nruns);
+  std::vector<dgk::FieldArgs> fa(3 * b->nruns);
+  for (int r = 0; r < b->nruns; ++r) {
+    dg_ctx* c = b->runs[r];
+    void* B = c->ws + c->L.off_B;
+    void* C = c->ws + c->L.off_C;
+    double* E = c->at<double>(c->L.off_E);
+    double* part = c->at<double>(c->L.off_part);
+    const void* ins[3] = {f[r], B, C};
+    void* outs[3] = {B, C, f[r]};
+    const double cu[3] = {0.0, 0.75, 1.0 / 3.0}, ci[3] = {1.0, 0.25, 2.0 / 3.0};
+    const double cd[3] = {dt[r], 0.25 * dt[r], 2.0 / 3.0 * dt[r]};
+    for (int k = 0; k < 3; ++k) {
+      fill_pack(c, &args[k * b->nruns + r], ins[k], f[r], outs[k], E, part, cu[k], ci[k], cd[k]);
+      fill_field(c, &fa[k * b->nruns + r], E, nullptr, k == 2);
+    }
+  }
+  DGB_HIP(b, hipMemcpyAsync(b->d_args, args.data(), args.size() * sizeof(args[0]), hipMemcpyHostToDevice, b->stream));
+  DGB_HIP(b, hipMemcpyAsync(b->d_fa, fa.data(), fa.size() * sizeof(fa[0]), hipMemcpyHostToDevice, b->stream));
+  DGB_HIP(b, hipStreamSynchronize(b->stream));
+  return DG_OK;
+}
+
+dg_status enqueue_batch_step(dg_batch* b, bool diag) {
+  for (int k = 0; k < 3; ++k) {
+    DGB_HIP(b, dgk::launch_stage_batched(k > 0, b->d_args + k * b->nruns, b->d_kind, b->d_items, b->d_xcd, b->grid, b->stream));
+    DGB_HIP(b, dgk::launch_field_batched(b->d_fa + k * b->nruns, b->d_xitems, b->nxitems, b->nruns, b->max_pmax, b->stream));
+  }
+  if (diag) {
+    for (int r = 0; r < b->nruns; ++r) {
+      dg_ctx* c = b->runs[r];
+      dg_status s = moments(c, b->g_f[r]);
+      if (s != DG_OK) return bfail(b, s, c->err);
+    }
+  }
+  return DG_OK;
+}
+
+dg_status build_batch_graph(dg_batch* b, void* const* f, const double* dt, bool diag) {
+  bool same = b->gexec && b->g_diag == diag;
+  for (int r = 0; same && r < b->nruns; ++r) same = b->g_f[r] == f[r] && b->g_dt[r] == dt[r];
+  if (same) return DG_OK;
+  if (b->gexec) {
+    hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  b->g_f.assign(f, f + b->nruns);
+  b->g_dt.assign(dt, dt + b->nruns);
+  b->g_diag = diag;
+  dg_status s = upload_args(b, f, dt);
+  if (s != DG_OK) return s;
+  DGB_HIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  s = enqueue_batch_step(b, diag);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (s != DG_OK) {
+    if (g) hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return bfail(b, DG_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->gexec = nullptr;
+    return bfail(b, DG_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  return DG_OK;
+}
+
+// Field of every run's initial state and the per-run CFL check.
+dg_status batch_begin(dg_batch* b, void* const* f, const double* dt) {
+  DGB_HIP(b, hipEventRecord(b->ev_in, b->user));
+  DGB_HIP(b, hipStreamWaitEvent(b->stream, b->ev_in, 0));
+  for (int r = 0; r < b->nruns; ++r) {
+    dg_ctx* c = b->runs[r];
+    if (!f[r]) return bfail(b, DG_ERR_INVALID, "f[r] is NULL");
+    if (!(dt[r] > 0.0) || !std::isfinite(dt[r])) return bfail(b, DG_ERR_INVALID, "dt[r] must be positive and finite");
+    dg_status s = density(c, f[r]);
+    if (s == DG_OK) s = field(c, c->at<double>(c->L.off_E), nullptr, false);
+    if (s != DG_OK) return bfail(b, s, c->err);
+  }
+  std::vector<double> last(8 * b->nruns);
+  for (int r = 0; r < b->nruns; ++r)
+    DGB_HIP(b, hipMemcpyAsync(&last[8 * r], b->runs[r]->at<double>(b->runs[r]->L.off_last), 64, hipMemcpyDeviceToHost, b->stream));
+  DGB_HIP(b, hipStreamSynchronize(b->stream));
+  for (int r = 0; r < b->nruns; ++r) {
+    if (!std::isfinite(last[8 * r + 5]) || last[8 * r + 6] == 0.0) {
+      char buf[96];
+      std::snprintf(buf, sizeof(buf), "run %d: initial field is not finite", r);
+      return bfail(b, DG_ERR_NONFINITE, buf);
+    }
+    const double dtm = dg_dt_max(b->runs[r], last[8 * r + 5]);
+    if (dt[r] > dtm) {
+      char buf[128];
+      std::snprintf(buf, sizeof(buf), "run %d: dt = %.6g exceeds the CFL bound %.6g", r, dt[r], dtm);
+      return bfail(b, DG_ERR_CFL, buf);
+    }
+  }
+  return DG_OK;
+}
+
+dg_status batch_leave(dg_batch* b) {
+  DGB_HIP(b, hipEventRecord(b->ev_out, b->stream));
+  DGB_HIP(b, hipStreamWaitEvent(b->user, b->ev_out, 0));
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dg_batch_workspace_bytes(const dg_config* cfgs, int32_t nruns) {
+  if (!cfgs || nruns <= 0) return 0;
+  for (int r = 0; r < nruns; ++r) {
+    dg_status st;
+    if (check_cfg(&cfgs[r], &st) || cfgs[r].storage != DG_F32) return 0;
+  }
+  return batch_layout(cfgs, nruns).total;
+}
+
+dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, size_t workspace_bytes,
+                        void* hip_stream, dg_batch** out) {
+  auto init_fail = [](dg_status s, const std::string& m) {
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    g_init_error = m;
+    return s;
+  };
+  if (!out) return init_fail(DG_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!cfgs || nruns <= 0) return init_fail(DG_ERR_INVALID, "need nruns >= 1 configurations");
+  for (int r = 0; r < nruns; ++r) {
+    dg_status st;
+    if (const char* why = check_cfg(&cfgs[r], &st)) return init_fail(st, std::string("run ") + std::to_string(r) + ": " + why);
+    if (cfgs[r].storage != DG_F32) return init_fail(DG_ERR_UNSUPPORTED, "batched runs use FP32 storage");
+  }
+  const BatchLayout BL = batch_layout(cfgs, nruns);
+  if (!workspace) return init_fail(DG_ERR_INVALID, "workspace is NULL");
+  if (workspace_bytes < BL.total) return init_fail(DG_ERR_OOM, "workspace smaller than dg_batch_workspace_bytes()");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return init_fail(DG_ERR_INVALID, "workspace must be 256-byte aligned");
+  dg_batch* b = new (std::nothrow) dg_batch();
+  if (!b) return init_fail(DG_ERR_INVALID, "host allocation failed");
+  b->nruns = nruns;
+  b->ws = static_cast<char*>(workspace);
+  b->user = static_cast<hipStream_t>(hip_stream);
+  b->run_off = BL.run_off;
+  auto cleanup = [&](dg_status s, const std::string& m) {
+    for (dg_ctx* c : b->runs) delete c;
+    if (b->stream) hipStreamDestroy(b->stream);
+    if (b->ev_in) hipEventDestroy(b->ev_in);
+    if (b->ev_out) hipEventDestroy(b->ev_out);
+    delete b;
+    return init_fail(s, m);
+  };
+  hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess) return cleanup(DG_ERR_DEVICE, "hipStreamCreate");
+  if ((e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming)) != hipSuccess) return cleanup(DG_ERR_DEVICE, "hipEventCreate");
+  if ((e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming)) != hipSuccess) return cleanup(DG_ERR_DEVICE, "hipEventCreate");
+  for (int r = 0; r < nruns; ++r) {
+    dg_ctx* c = nullptr;
+    std::string err;
+    dg_status st = make_ctx(&cfgs[r], b->ws + BL.run_off[r], b->stream, false, &c, &err);
+    if (st != DG_OK) return cleanup(st, "run " + std::to_string(r) + ": " + err);
+    b->runs.push_back(c);
+  }
+  b->d_args = reinterpret_cast<dgk::StageArgs<float>*>(b->ws + BL.args);
+  b->d_kind = reinterpret_cast<int*>(b->ws + BL.kind);
+  b->d_items = reinterpret_cast<int2*>(b->ws + BL.items);
+  b->d_xcd = reinterpret_cast<int*>(b->ws + BL.xcd);
+  b->d_fa = reinterpret_cast<dgk::FieldArgs*>(b->ws + BL.fa);
+  b->d_xitems = reinterpret_cast<int2*>(b->ws + BL.xitems);
+  // work lists: runs by decreasing tile cost, tiles in order (cost-sorted),
+  // or tiles of all runs interleaved round-robin (run-interleaved)
+  std::vector<int> kind(nruns), byc(nruns);
+  std::vector<int2> xitems;
+  for (int r = 0; r < nruns; ++r) {
+    kind[r] = 10 * cfgs[r].n + cfgs[r].nv;
+    byc[r] = r;
+    for (int ix = 0; ix < b->runs[r]->L.Nx; ++ix) xitems.push_back(make_int2(r, ix));
+    b->max_pmax = std::max(b->max_pmax, b->runs[r]->L.pmax);
+  }
+  std::stable_sort(byc.begin(), byc.end(), [&](int p, int q) {
+    const Layout &A = b->runs[p]->L, &B = b->runs[q]->L;
+    return static_cast<double>(A.dof) / A.ntiles > static_cast<double>(B.dof) / B.ntiles;
+  });
+  for (int r : byc)
+    for (int t = 0; t < b->runs[r]->L.ntiles; ++t) b->items_cost.push_back(make_int2(r, t));
+  {
+    std::vector<int> next(nruns, 0);
+    bool any = true;
+    while (any) {
+      any = false;
+      for (int r : byc)
+        if (next[r] < b->runs[r]->L.ntiles) {
+          b->items_rr.push_back(make_int2(r, next[r]++));
+          any = true;
+        }
+    }
+  }
+  b->nitems = static_cast<int>(b->items_cost.size());
+  b->nxitems = static_cast<int>(xitems.size());
+  if ((e = hipMemcpyAsync(b->d_kind, kind.data(), nruns * sizeof(int), hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(b->d_xitems, xitems.data(), xitems.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream)) != hipSuccess)
+    return cleanup(DG_ERR_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if ((e = hipGetDevice(&dev)) != hipSuccess || (e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
+    return cleanup(DG_ERR_DEVICE, std::string("device query: ") + hipGetErrorString(e));
+  b->cus = prop.multiProcessorCount;
+  b->occ[0] = dgk::batched_occupancy(false);
+  b->occ[1] = dgk::batched_occupancy(true);
+  const int occ = std::max(1, std::min(b->occ[0], b->occ[1]));
+  b->grid = b->cus * occ;
+  if (upload_items(b) != DG_OK) return cleanup(DG_ERR_DEVICE, b->err);
+  *out = b;
+  return DG_OK;
+}
+
+dg_status dg_batch_destroy(dg_batch* b) {
+  if (!b) return DG_OK;
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  for (dg_ctx* c : b->runs) dg_destroy(c);
+  hipEventDestroy(b->ev_in);
+  hipEventDestroy(b->ev_out);
+  hipStreamDestroy(b->stream);
+  delete b;
+  return e == hipSuccess ? DG_OK : DG_ERR_DEVICE;
+}
+
+dg_status dg_batch_rk_step(dg_batch* b, void* const* f, const double* dt, int32_t nsteps, dg_diag* host_diag) {
+  if (!b) return DG_ERR_INVALID;
+  if (!f || !dt) return bfail(b, DG_ERR_INVALID, "f and dt must be non-NULL");
+  if (nsteps < 0) return bfail(b, DG_ERR_INVALID, "nsteps < 0");
+  if (nsteps == 0) return DG_OK;
+  dg_status s = batch_begin(b, f, dt);
+  if (s != DG_OK) {
+    batch_leave(b);
+    return s;
+  }
+  const bool diag = host_diag != nullptr;
+  s = build_batch_graph(b, f, dt, diag);
+  if (s != DG_OK) return s;
+  int done = 0;
+  bool bad = false;
+  while (done < nsteps) {
+    const int chunk = std::min(nsteps - done, dgk::kRing);
+    if (diag)
+      for (dg_ctx* c : b->runs) DGB_HIP(b, dgk::launch_reset_counter(c->at<int>(c->L.off_ctr), b->stream));
+    for (int k = 0; k < chunk; ++k) DGB_HIP(b, hipGraphLaunch(b->gexec, b->stream));
+    if (diag) {
+      std::vector<double> ring(static_cast<size_t>(chunk) * 8);
+      for (int r = 0; r < b->nruns; ++r) {
+        dg_ctx* c = b->runs[r];
+        DGB_HIP(b, hipMemcpyAsync(ring.data(), c->at<double>(c->L.off_ring), ring.size() * 8, hipMemcpyDeviceToHost, b->stream));
+        DGB_HIP(b, hipStreamSynchronize(b->stream));
+        for (int k = 0; k < chunk; ++k) {
+          dg_diag* d = &host_diag[static_cast<size_t>(r) * nsteps + done + k];
+          copy_record(&ring[static_cast<size_t>(k) * 8], c->t + (done + k + 1) * dt[r], d);
+          d->step = done + k;
+          if (!d->finite) bad = true;
+        }
+      }
+    }
+    done += chunk;
+  }
+  for (int r = 0; r < b->nruns; ++r) b->runs[r]->t += nsteps * dt[r];
+  s = batch_leave(b);
+  if (s != DG_OK) return s;
+  if (diag) DGB_HIP(b, hipStreamSynchronize(b->stream));
+  if (bad) return bfail(b, DG_ERR_NONFINITE, "a step produced non-finite diagnostics");
+  return DG_OK;
+}
+
+dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t reps, double* best_ms) {
+  if (!b) return DG_ERR_INVALID;
+  if (!f || !dt || reps < 1) return bfail(b, DG_ERR_INVALID, "need f, dt and reps >= 1");
+  dg_status s = batch_begin(b, f, dt);
+  if (s != DG_OK) {
+    batch_leave(b);
+    return s;
+  }
+  hipEvent_t e0, e1;
+  DGB_HIP(b, hipEventCreate(&e0));
+  DGB_HIP(b, hipEventCreate(&e1));
+  const int occ = std::max(1, std::min(b->occ[0], b->occ[1]));
+  double best = 1e300;
+  int best_grid = b->grid, best_order = b->order;
+  for (int order = 0; order < 2 && s == DG_OK; ++order) {
+    b->order = order;
+    s = upload_items(b);
+    for (int w = 1; w <= occ && s == DG_OK; ++w) {
+      b->grid = b->cus * w;
+      if (b->gexec) {
+        hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+      }
+      s = build_batch_graph(b, f, dt, false);
+      if (s != DG_OK) break;
+      DGB_HIP(b, hipGraphLaunch(b->gexec, b->stream));   // warm-up
+      DGB_HIP(b, hipEventRecord(e0, b->stream));
+      for (int k = 0; k < reps; ++k) DGB_HIP(b, hipGraphLaunch(b->gexec, b->stream));
+      DGB_HIP(b, hipEventRecord(e1, b->stream));
+      DGB_HIP(b, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      DGB_HIP(b, hipEventElapsedTime(&ms, e0, e1));
+      if (ms / reps < best) {
+        best = ms / reps;
+        best_grid = b->grid;
+        best_order = order;
+      }
+      for (int r = 0; r < b->nruns; ++r) b->runs[r]->t += (reps + 1) * dt[r];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (s != DG_OK) return s;
+  b->grid = best_grid;
+  b->order = best_order;
+  s = upload_items(b);
+  if (s != DG_OK) return s;
+  if (b->gexec) {
+    hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  if (best_ms) *best_ms = best;
+  return batch_leave(b);
+}
+
+int32_t dg_batch_grid(const dg_batch* b) { return b ? b->grid : 0; }
+
+const char* dg_batch_last_error(const dg_batch* b) {
+  if (b) return b->err.c_str();
+  std::lock_guard<std::mutex> lk(g_err_mu);
+  return g_init_error.c_str();
 }
 
 }  // extern "C"

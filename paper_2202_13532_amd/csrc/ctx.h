@@ -1,0 +1,66 @@
+// Internal: the context structure and the stage / field helpers shared by
+// the single-run entry points and the learned-correction entry points.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <string>
+
+#include "../../include/dg.h"
+#include "dg_host.h"
+
+namespace dgi {
+
+// Workspace layout derived from a validated configuration.
+struct Layout {
+  size_t esize = 0, dof = 0;
+  int naxes = 0, n = 0, Nx = 0, Nu = 1, Nv = 0, nvchunks = 0, pmax = 0;
+  int ntiles_slab = 0, ntiles = 0;
+  size_t off_B, off_C, off_part, off_mom, off_dens, off_E, off_cpart, off_mpart, off_coef, off_ring,
+      off_last, off_ctr, off_T, off_z1, off_wx, off_wu, off_wv, off_uc, off_vc, off_uc64, off_vc64, total;
+};
+
+}  // namespace dgi
+
+struct dg_ctx {
+  dg_config cfg{};
+  dgi::Layout L;
+  dgh::Basis basis;
+  double courant = 0.0;
+  double dx[3] = {0, 0, 0};
+  char* ws = nullptr;
+  hipStream_t user = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  bool owns_stream = true;
+  double t = 0.0;
+  std::string err = "no error";
+  // cached step graph
+  hipGraphExec_t gexec = nullptr;
+  const void* g_f = nullptr;
+  double g_dt = 0.0;
+  bool g_diag = false;
+
+  template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
+  bool f64() const { return cfg.storage == DG_F64; }
+};
+
+namespace dgi {
+
+dg_status fail(dg_ctx* c, dg_status s, const std::string& msg);
+dg_status hip_fail(dg_ctx* c, hipError_t e, const char* what);
+// out = c_un un + c_in fin + c_dt L(fin) with field E; density partials of out
+// into `partials` when non-NULL.
+dg_status stage(dg_ctx* c, const void* fin, const void* fun, void* out, const double* E, double* partials,
+                double c_un, double c_in, double c_dt);
+// Density partials of f (FP64) into the workspace.
+dg_status density(dg_ctx* c, const void* f);
+// Field solve from the workspace density partials.
+dg_status field(dg_ctx* c, double* E, double* coeffs, bool record);
+dg_status enter(dg_ctx* c);
+dg_status leave(dg_ctx* c);
+// Field of f, CFL check of dt (synchronises).
+dg_status begin_steps(dg_ctx* ctx, void* f, double dt, int32_t nsteps);
+void copy_record(const double* r, double t, dg_diag* out);
+
+}  // namespace dgi

@@ -162,27 +162,44 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t xelem_rsrc(const T* base, size
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base + ix * xstride), 0, static_cast<int>(bytes), kRsrcWord3);
 }
 
-// LDS row stride for the v exchange: at least TV*n + 2 and = 1 (mod 64), so
-// that with pencils numbered lane = pv*n + pr the address of node k of every
-// pencil, pr*ROW + pv*n + k = lane + k (mod 64), falls in distinct banks.
+// LDS row stride for the v exchange: the smallest R >= TV*n + 2 for which the
+// pencil start addresses pr*R + pv*n (lane = pv*n + pr) fall in distinct banks
+// modulo 64, so the n+2 pencil reads of a wave are free of bank conflicts.
 template <int N>
-constexpr int lds_row() { return (kWave / N) * N + 2 <= 65 ? 65 : 129; }
+constexpr int lds_row() {
+  constexpr int TV = kWave / N;
+  for (int R = TV * N + 2; R < TV * N + 2 + 128; ++R) {
+    bool seen[64] = {};
+    bool ok = true;
+    for (int pv = 0; pv < TV && ok; ++pv)
+      for (int pr = 0; pr < N && ok; ++pr) {
+        const int b = (pr * R + pv * N) % 64;
+        if (seen[b]) ok = false;
+        seen[b] = true;
+      }
+    if (ok) return R;
+  }
+  return TV * N + 2;
+}
+template <int N>
+constexpr int lds_words_2v() { return 3 * (N + 1) * lds_row<N>(); }
+template <int N>
+constexpr int lds_words_1v() { return (N + 1) * lds_row<N>(); }
 
 // -------------------------------------------------------------------------
 // 1D2V stage kernel.  state [Nx, N, Nu, N, Nv, N].  UN: stage reads u^n.
 // -------------------------------------------------------------------------
+// lds: lds_words_2v<N>() words (input rows + 2 result buffers; row N of each
+// is the scratch row of idle lanes); hbuf: N*N words.
 template <typename T, int N, bool UN>
-__global__ void __launch_bounds__(kWave, 2) stage2v_kernel(StageArgs<T> a) {
+__device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* lds, T* hbuf) {
   using B = Buf<T>;
   constexpr unsigned S = sizeof(T);
   constexpr int TV = kWave / N;
   constexpr int ROW = lds_row<N>();
-  __shared__ T lds[3 * (N + 1) * ROW]; // input rows + 2 result buffers; row N of each: scratch of idle lanes
-  __shared__ T hbuf[N * N];
   constexpr dgc::OpsC<N> K = dgc::make_ops<N>();
 
   const unsigned lane = threadIdx.x;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int vc = bid % a.nvchunks;
   const int t1 = bid / a.nvchunks;
   const int iu = t1 % a.Nu;
@@ -378,19 +395,24 @@ __global__ void __launch_bounds__(kWave, 2) stage2v_kernel(StageArgs<T> a) {
   finish_row(N - 1, accp, ((N - 1) & 1) ? lout1 : lout0);
 }
 
+template <typename T, int N, bool UN>
+__global__ void __launch_bounds__(kWave, 2) stage2v_kernel(StageArgs<T> a) {
+  __shared__ T lds[lds_words_2v<N>()];
+  __shared__ T hbuf[N * N];
+  stage2v_tile<T, N, UN>(a, xcd_remap(blockIdx.x, gridDim.x), lds, hbuf);
+}
+
 // -------------------------------------------------------------------------
 // 1D1V stage kernel.  state [Nx, N, Nv, N]; x speed v, v speed -E(x).
 // -------------------------------------------------------------------------
 template <typename T, int N, bool UN>
-__global__ void __launch_bounds__(kWave) stage1v_kernel(StageArgs<T> a) {
+__device__ __forceinline__ void stage1v_tile(const StageArgs<T> a, int bid, T* lds) {
   using B = Buf<T>;
   constexpr unsigned S = sizeof(T);
   constexpr int TV = kWave / N;
   constexpr int ROW = lds_row<N>();
-  __shared__ T lds[(N + 1) * ROW];
 
   const unsigned lane = threadIdx.x;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int vc = bid % a.nvchunks;
   const int ix = bid / a.nvchunks;
   const int iv0 = vc * TV;
@@ -477,6 +499,12 @@ __global__ void __launch_bounds__(kWave) stage1v_kernel(StageArgs<T> a) {
       if (lane == 0) a.partials[static_cast<size_t>(ix * N + jx) * a.nvchunks + vc] = s;
     }
   }
+}
+
+template <typename T, int N, bool UN>
+__global__ void __launch_bounds__(kWave) stage1v_kernel(StageArgs<T> a) {
+  __shared__ T lds[lds_words_1v<N>()];
+  stage1v_tile<T, N, UN>(a, xcd_remap(blockIdx.x, gridDim.x), lds);
 }
 
 // -------------------------------------------------------------------------
@@ -583,10 +611,10 @@ constexpr int kFieldB = 256;
 
 constexpr int kFieldA = 256;
 
-__global__ void __launch_bounds__(kFieldA) fieldA_kernel(FieldArgs a) {
+__device__ __forceinline__ void fieldA_body(const FieldArgs& a, int ix) {
   __shared__ double dens[kMaxN];
   __shared__ double red[kFieldA / kWave][kMaxN];
-  const int ix = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave, n = a.n;
+  const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave, n = a.n;
   // thread-strided partial sums for all x nodes at once (n loads in flight),
   // wave sums, then the waves' results added in order
   double s[kMaxN];
@@ -631,7 +659,7 @@ __global__ void __launch_bounds__(kFieldA) fieldA_kernel(FieldArgs a) {
   }
 }
 
-__global__ void __launch_bounds__(kFieldB) fieldB_kernel(FieldArgs a) {
+__device__ __forceinline__ void fieldB_body(const FieldArgs& a) {
   extern __shared__ double csh[];          // 2 * pmax coefficients
   __shared__ double red[2][kFieldB];
   const int tid = threadIdx.x;
@@ -722,6 +750,9 @@ __global__ void __launch_bounds__(kFieldB) fieldB_kernel(FieldArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(kFieldA) fieldA_kernel(FieldArgs a) { fieldA_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(kFieldB) fieldB_kernel(FieldArgs a) { fieldB_body(a); }
+
 constexpr int kFieldThreads = 256;
 
 __global__ void moments_reduce_kernel(const double* mom, int ntiles, double* ring, const int* counter) {
@@ -761,6 +792,58 @@ __global__ void moments_reduce_kernel(const double* mom, int ntiles, double* rin
 }
 
 __global__ void reset_counter_kernel(int* c) { *c = 0; }
+
+// -------------------------------------------------------------------------
+// Batched persistent stage kernel: many independent runs (1D1V and 1D2V, any
+// n in 2..9, FP32 storage) in one launch.  The host builds a work list of
+// (run, tile) items ordered by decreasing tile cost and split into 8
+// contiguous ranges, one per XCD; work-group b serves range b % 8 with a
+// stride of the number of work-groups on that XCD, so the waves of one XCD
+// walk neighbouring tiles together.  Each item runs the same tile code as the
+// single-run kernels.
+// -------------------------------------------------------------------------
+template <int N>
+constexpr int lds_words_any() { return lds_words_2v<N>() > lds_words_1v<N>() ? lds_words_2v<N>() : lds_words_1v<N>(); }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kBatchLds = cmax(cmax(cmax(lds_words_any<2>(), lds_words_any<3>()), cmax(lds_words_any<4>(), lds_words_any<5>())),
+                               cmax(cmax(lds_words_any<6>(), lds_words_any<7>()), cmax(lds_words_any<8>(), lds_words_any<9>())));
+
+template <bool UN>
+__global__ void __launch_bounds__(kWave, 2) stage_batched_kernel(const StageArgs<float>* __restrict__ runs,
+                                                                  const int* __restrict__ kind,
+                                                                  const int2* __restrict__ items,
+                                                                  const int* __restrict__ xcd_begin) {
+  __shared__ float lds[kBatchLds];
+  __shared__ float hbuf[kMaxN * kMaxN];
+  const int b = blockIdx.x, c = b & 7, slot = b >> 3, g = gridDim.x;
+  const int slots = (g >> 3) + (c < (g & 7) ? 1 : 0);
+  const int end = xcd_begin[c + 1];
+  for (int i = xcd_begin[c] + slot; i < end; i += slots) {
+    const int2 it = items[i];
+    const int r = it.x, t = it.y;
+    const StageArgs<float> a = runs[r];
+    switch (kind[r]) {   // 10 * n + nv
+#define DG_BATCH_CASE(NN)                                                          \
+  case 10 * NN + 2: stage2v_tile<float, NN, UN>(a, t, lds, hbuf); break;           \
+  case 10 * NN + 1: stage1v_tile<float, NN, UN>(a, t, lds); break;
+      DG_BATCH_CASE(2) DG_BATCH_CASE(3) DG_BATCH_CASE(4) DG_BATCH_CASE(5)
+      DG_BATCH_CASE(6) DG_BATCH_CASE(7) DG_BATCH_CASE(8) DG_BATCH_CASE(9)
+#undef DG_BATCH_CASE
+      default: break;
+    }
+    wave_lds_order();
+  }
+}
+
+// Batched field solve: block q of fieldA serves (run, x element) item q;
+// block r of fieldB serves run r.
+__global__ void __launch_bounds__(kFieldA) fieldA_batched_kernel(const FieldArgs* __restrict__ fa, const int2* __restrict__ items) {
+  const int2 it = items[blockIdx.x];
+  fieldA_body(fa[it.x], it.y);
+}
+__global__ void __launch_bounds__(kFieldB) fieldB_batched_kernel(const FieldArgs* __restrict__ fa) {
+  fieldB_body(fa[blockIdx.x]);
+}
 
 // -------------------------------------------------------------------------
 // Host launchers.
@@ -838,6 +921,28 @@ hipError_t launch_field(const FieldArgs& a, hipStream_t s) {
 hipError_t launch_moments_reduce(const double* mom, int ntiles, double* ring, const int* counter, hipStream_t s) {
   hipLaunchKernelGGL(moments_reduce_kernel, dim3(1), dim3(kFieldThreads), 0, s, mom, ntiles, ring, counter);
   return hipGetLastError();
+}
+
+hipError_t launch_stage_batched(bool un, const StageArgs<float>* runs, const int* kind, const int2* items,
+                                const int* xcd_begin, int grid, hipStream_t s) {
+  if (un) hipLaunchKernelGGL(stage_batched_kernel<true>, dim3(grid), dim3(kWave), 0, s, runs, kind, items, xcd_begin);
+  else hipLaunchKernelGGL(stage_batched_kernel<false>, dim3(grid), dim3(kWave), 0, s, runs, kind, items, xcd_begin);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_batched(const FieldArgs* fa, const int2* xitems, int nxitems, int nruns, int max_pmax, hipStream_t s) {
+  hipLaunchKernelGGL(fieldA_batched_kernel, dim3(nxitems), dim3(kFieldA), 0, s, fa, xitems);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fieldB_batched_kernel, dim3(nruns), dim3(kFieldB), 2 * max_pmax * sizeof(double), s, fa);
+  return hipGetLastError();
+}
+
+int batched_occupancy(bool un) {
+  int nb = 0;
+  hipError_t e = un ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_batched_kernel<true>, kWave, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_batched_kernel<false>, kWave, 0);
+  return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_reset_counter(int* counter, hipStream_t s) {

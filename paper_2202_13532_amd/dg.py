@@ -20,7 +20,8 @@ STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_INVALID", 2: "DG_ERR_UNSUPPORTED", 3: "DG
 
 EXPORTED = ["dg_workspace_bytes", "dg_init", "dg_destroy", "dg_rhs", "dg_poisson", "dg_rk_step",
             "dg_diagnostics", "dg_profile_step", "dg_dt_max", "dg_node_coords", "dg_last_error", "dg_basis",
-            "dg_connection_tensor", "dg_courant_number"]
+            "dg_connection_tensor", "dg_courant_number", "dg_batch_workspace_bytes", "dg_batch_init",
+            "dg_batch_destroy", "dg_batch_rk_step", "dg_batch_tune", "dg_batch_grid", "dg_batch_last_error"]
 
 
 class dg_config(ctypes.Structure):
@@ -75,6 +76,13 @@ def lib():
         "dg_basis": (I, [I, dp, dp, dp, dp, dp]),
         "dg_connection_tensor": (I, [I, I, D, D, I, dp]),
         "dg_courant_number": (D, [I]),
+        "dg_batch_workspace_bytes": (S, [cfgp, I]),
+        "dg_batch_init": (I, [cfgp, I, P, S, P, ctypes.POINTER(P)]),
+        "dg_batch_destroy": (I, [P]),
+        "dg_batch_rk_step": (I, [P, ctypes.POINTER(P), dp, I, diagp]),
+        "dg_batch_tune": (I, [P, ctypes.POINTER(P), dp, I, dp]),
+        "dg_batch_grid": (I, [P]),
+        "dg_batch_last_error": (ctypes.c_char_p, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -267,3 +275,103 @@ class Solver:
 
     def dt_max(self, max_abs_E=0.0):
         return dg_dt_max(self.ctx, max_abs_E)
+
+
+# ---------------- batches ----------------
+
+def _bcheck(status, b=None):
+    if status != DG_OK:
+        raise DGError(status, lib().dg_batch_last_error(b).decode())
+
+
+def dg_batch_workspace_bytes(cfgs):
+    arr = (dg_config * len(cfgs))(*cfgs)
+    return int(lib().dg_batch_workspace_bytes(arr, len(cfgs)))
+
+
+def dg_batch_init(cfgs, workspace, stream=None):
+    arr = (dg_config * len(cfgs))(*cfgs)
+    b = ctypes.c_void_p()
+    st = lib().dg_batch_init(arr, len(cfgs), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                             ctypes.c_void_p(stream), ctypes.byref(b))
+    _bcheck(st, None)
+    return b
+
+
+def dg_batch_destroy(b):
+    _bcheck(lib().dg_batch_destroy(b), None)
+
+
+def _ptr_array(states):
+    return (ctypes.c_void_p * len(states))(*[t.data_ptr() for t in states])
+
+
+def dg_batch_rk_step(b, states, dts, nsteps, diag=False):
+    dt = np.ascontiguousarray(dts, dtype=np.float64)
+    recs = (dg_diag * (len(states) * nsteps))() if (diag and nsteps > 0) else None
+    _bcheck(lib().dg_batch_rk_step(b, _ptr_array(states), _dptr(dt), int(nsteps), recs), b)
+    if recs is None:
+        return None
+    return [[recs[r * nsteps + k].as_dict() for k in range(nsteps)] for r in range(len(states))]
+
+
+def dg_batch_tune(b, states, dts, reps):
+    dt = np.ascontiguousarray(dts, dtype=np.float64)
+    best = np.zeros(1)
+    _bcheck(lib().dg_batch_tune(b, _ptr_array(states), _dptr(dt), int(reps), _dptr(best)), b)
+    return float(best[0])
+
+
+def dg_batch_grid(b):
+    return int(lib().dg_batch_grid(b))
+
+
+class Batch:
+    """Many independent runs stepped by one persistent launch per RK stage."""
+
+    def __init__(self, configs, device="cuda"):
+        import torch
+        self.torch = torch
+        self.cfgs = list(configs)
+        nbytes = dg_batch_workspace_bytes(self.cfgs)
+        if nbytes == 0:
+            raise DGError(DG_ERR_INVALID, "invalid batch configuration")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws = self.workspace[off:off + nbytes]
+        self.b = dg_batch_init(self.cfgs, self.ws, torch.cuda.current_stream(self.device).cuda_stream)
+        self.shapes = []
+        for c in self.cfgs:
+            ne = [c.nelem[a] for a in range(1 + c.nv)]
+            self.shapes.append(tuple(x for N in ne for x in (N, c.n)))
+
+    def close(self):
+        if getattr(self, "b", None) is not None:
+            dg_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, states):
+        if len(states) != len(self.cfgs):
+            raise DGError(DG_ERR_INVALID, "one state per run")
+        for t, shp in zip(states, self.shapes):
+            if t.dtype != self.torch.float32 or not t.is_contiguous() or tuple(t.shape) != shp or t.device.type != "cuda":
+                raise DGError(DG_ERR_INVALID, "state must be contiguous float32 of shape %s" % (shp,))
+
+    def step(self, states, dts, nsteps=1, diag=False):
+        self._check(states)
+        return dg_batch_rk_step(self.b, states, dts, nsteps, diag)
+
+    def tune(self, states, dts, reps=3):
+        self._check(states)
+        return dg_batch_tune(self.b, states, dts, reps)
+
+    @property
+    def grid(self):
+        return dg_batch_grid(self.b)

@@ -84,7 +84,38 @@ def initial_state(wl, axes_nodes, xp):
         return inputs.ring_perturbed(c[0], c[1], c[2], a["k"], a.get("eps", 1e-3), a.get("r0", 3.0), xp)
     if wl.ic == "maxwell_multimode":
         return inputs.maxwell_multimode(c[0], c[1], c[2], a["k1"], a["seed"], a.get("eps", 1e-3), 8, xp)
+    if wl.ic == "maxwell_1v":
+        return inputs.maxwellian_1d(c[1], a["vt"], xp) * (1.0 + a["eps"] * xp.cos(a["k"] * c[0]))
+    if wl.ic == "maxwell_2v":
+        return inputs.maxwellian_2d(c[1], c[2], a["vt"], xp) * (1.0 + a["eps"] * xp.cos(a["k"] * c[0]))
     if wl.ic == "mixture":
         return inputs.mixture(c[0], c[1], c[2], a.get("a", 0.5), a.get("vt", 1.0),
                               a.get("k1", 0.5), a.get("eps", 1e-3), 3.0, xp)
     raise ValueError(wl.ic)
+
+
+def uneven_sweep(nruns=64, seed0=1000):
+    """Batched uneven sweep: half 1D1V, half 1D2V; per run r a generator seeded
+    with seed0 + r draws Nx in {8..64}, Nv in {16..64} elements per velocity
+    axis, n in {4..9}, k in [0.1, 0.6], thermal speed in [0.5, 1.5] and (1D2V)
+    omega_c in {0, 0.5, 1}; L = 2 pi / k, velocity box +-8 vt, FP32."""
+    import numpy as np
+    out = []
+    for r in range(nruns):
+        g = np.random.default_rng(seed0 + r)
+        nv = 1 if r < nruns // 2 else 2
+        Nx = int(g.integers(8, 65))
+        Nv = int(g.integers(16, 65))
+        n = int(g.integers(4, 10))
+        k = float(g.uniform(0.1, 0.6))
+        vt = float(g.uniform(0.5, 1.5))
+        wc = float(g.choice([0.0, 0.5, 1.0])) if nv == 2 else 0.0
+        V = 8.0 * vt
+        if nv == 1:
+            wl = Workload("sweep_%d" % r, 1, n, [Nx, Nv], [0.0, -V], [2 * math.pi / k, V], 0.0, "f32", 20,
+                          ic="maxwell_1v", ic_args={"k": k, "vt": vt, "eps": 0.01})
+        else:
+            wl = Workload("sweep_%d" % r, 2, n, [Nx, Nv, Nv], [0.0, -V, -V], [2 * math.pi / k, V, V], wc, "f32", 20,
+                          ic="maxwell_2v", ic_args={"k": k, "vt": vt, "eps": 0.01})
+        out.append(wl)
+    return out

@@ -1,0 +1,125 @@
+"""Batched persistent launch: every run equals its solo run and the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import grid, lgl, rk  # noqa: E402
+from paper_2202_13532_amd import dg, inputs, workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [
+    # nv, n, nelem, lo, hi, wc
+    (1, 4, [5, 21], [0.0, -6.0], [4 * math.pi, 6.0], 0.0),
+    (2, 8, [3, 4, 11], [0.0, -8.0, -8.0], [2 * math.pi, 8.0, 8.0], 1.0),
+    (1, 7, [3, 10], [0.0, -5.0], [6.0, 5.0], 0.0),
+    (2, 5, [2, 3, 13], [0.0, -6.0, -6.0], [5.0, 6.0, 6.0], 0.5),
+    (2, 9, [2, 2, 8], [0.0, -8.0, -8.0], [20.0, 8.0, 8.0], 0.0),
+    (1, 2, [4, 70], [0.0, -4.0], [3.0, 4.0], 0.0),
+]
+
+
+def _state(case, seed):
+    nv, n, nelem, lo, hi, wc = case
+    g = grid.PhaseGrid(nv, n, nelem, lo, hi, wc)
+    c = g.coords()
+    k = 2 * math.pi / (hi[0] - lo[0])
+    if nv == 1:
+        f = inputs.maxwellian_1d(c[1], 1.0) * (1 + 0.05 * np.cos(k * c[0]))
+    else:
+        f = inputs.maxwellian_2d(c[1], c[2], 1.2) * (1 + 0.05 * np.cos(k * c[0]))
+    f = np.broadcast_to(f, g.shape) * (1 + 0.01 * inputs.random_nodal(g.shape, seed))
+    return g, np.ascontiguousarray(f)
+
+
+def test_batch_equals_solo_runs_and_oracle():
+    cfgs = [dg.make_config(nv, n, ne, lo, hi, wc) for nv, n, ne, lo, hi, wc in SMALL]
+    B = dg.Batch(cfgs)
+    grids, host, dev, dts = [], [], [], []
+    for i, case in enumerate(SMALL):
+        g, f = _state(case, 10 + i)
+        grids.append(g)
+        host.append(f)
+        dev.append(torch.from_numpy(f).float().cuda())
+        s = dg.Solver(*case[:6])
+        dts.append(0.4 * s.dt_max(0.2))
+        s.close()
+    solo = [d.clone() for d in dev]
+    B.step(dev, dts, 2)
+    for i, case in enumerate(SMALL):
+        s = dg.Solver(*case[:6])
+        s.step(solo[i], dts[i], 2)
+        s.close()
+        a, b = dev[i].cpu().numpy().astype(np.float64), solo[i].cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(a - b)) <= 1e-6 * np.max(np.abs(b)), i
+        # oracle: two FP64 steps from the FP32-rounded initial state
+        f0 = torch.from_numpy(host[i]).float().double().numpy()
+        ref = f0
+        for _ in range(2):
+            ref = rk.ssprk3_step(grids[i], lgl.operators(case[1]), ref, dts[i])
+        assert np.linalg.norm(a - ref) / np.linalg.norm(ref) < 1e-5, i
+    B.close()
+
+
+def test_batch_bitwise_equal_to_solo():
+    case = SMALL[1]
+    cfg = dg.make_config(*case[:6])
+    B = dg.Batch([cfg])
+    g, f = _state(case, 3)
+    a = torch.from_numpy(f).float().cuda()
+    b = a.clone()
+    s = dg.Solver(*case[:6])
+    dt = 0.4 * s.dt_max(0.2)
+    B.step([a], [dt], 3)
+    s.step(b, dt, 3)
+    assert torch.equal(a, b)
+    s.close()
+    B.close()
+
+
+def test_batch_diagnostics_and_cfl_errors():
+    cfgs = [dg.make_config(*c[:6]) for c in SMALL[:3]]
+    B = dg.Batch(cfgs)
+    dev, dts = [], []
+    for i, case in enumerate(SMALL[:3]):
+        _, f = _state(case, 20 + i)
+        dev.append(torch.from_numpy(f).float().cuda())
+        s = dg.Solver(*case[:6])
+        dts.append(0.4 * s.dt_max(0.2))
+        s.close()
+    m0 = [None] * 3
+    recs = B.step(dev, dts, 4, diag=True)
+    assert len(recs) == 3 and all(len(r) == 4 for r in recs)
+    for r in recs:
+        assert all(x["finite"] == 1 for x in r)
+        ms = [x["mass"] for x in r]
+        assert max(ms) - min(ms) < 1e-6 * abs(ms[0])
+    bad = list(dts)
+    bad[1] = 100.0
+    with pytest.raises(dg.DGError) as e:
+        B.step(dev, bad, 1)
+    assert e.value.status == dg.DG_ERR_CFL
+    best = B.tune(dev, dts, 1)
+    assert best > 0 and B.grid > 0
+    B.close()
+
+
+def test_uneven_sweep_64_runs_conserves_mass():
+    wls = workloads.uneven_sweep(64)
+    cfgs = [dg.make_config(w.nv, w.n, w.nelem, w.lo, w.hi, w.omega_c) for w in wls]
+    B = dg.Batch(cfgs)
+    dev, dts = [], []
+    for w in wls:
+        s = dg.Solver(w.nv, w.n, w.nelem, w.lo, w.hi, w.omega_c)
+        nodes = [torch.from_numpy(s.nodes(a)).cuda() for a in range(1 + w.nv)]
+        dev.append(workloads.initial_state(w, nodes, torch).float().contiguous())
+        dts.append(0.9 * s.dt_max(0.05))
+        s.close()
+    recs = B.step(dev, dts, 2, diag=True)
+    for r, w in zip(recs, wls):
+        assert r[-1]["finite"] == 1
+        assert abs(r[-1]["mass"] - r[0]["mass"]) < 1e-6 * abs(r[0]["mass"]), w.name
+    B.close()

@@ -103,6 +103,66 @@ def cpu_baseline(wl, budget_s=12.0):
                       % (reps, nx_sub, wl.nelem[0], dof_inner, el)}
 
 
+def bench_sweep(args):
+    """Uneven batch of 64 runs (32 x 1D1V, 32 x 1D2V, n 4..9): one persistent
+    stage launch per RK stage for all runs, against the same runs stepped one
+    after another with their own graphs."""
+    import torch
+    from paper_2202_13532_amd import dg
+    from paper_2202_13532_amd import workloads as W
+    wls = W.uneven_sweep(64)
+    cfgs = [dg.make_config(w.nv, w.n, w.nelem, w.lo, w.hi, w.omega_c) for w in wls]
+    solos = [dg.Solver(w.nv, w.n, w.nelem, w.lo, w.hi, w.omega_c) for w in wls]
+    states, dts = [], []
+    for w, so in zip(wls, solos):
+        f = make_state(torch, so, w)
+        E0 = so.poisson(f)
+        dts.append(w.cfl_fraction * so.dt_max(max(float(E0.abs().max()), 0.05)))
+        states.append(f)
+    dof = sum(w.dof() for w in wls)
+    print("[bench] sweep: %d runs, %d DOF" % (len(wls), dof), file=sys.stderr, flush=True)
+    b = dg.Batch(cfgs)
+    tuned_ms = b.tune(states, dts, 3)
+    if args.warmup > 0:
+        b.step(states, dts, args.warmup)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    b.step(states, dts, args.steps)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    # the same runs one after another (each with its own captured step graph)
+    for so, f, dt in zip(solos, states, dts):
+        so.step(f, dt, max(1, args.warmup))
+    torch.cuda.synchronize()
+    start.record()
+    for so, f, dt in zip(solos, states, dts):
+        so.step(f, dt, args.steps)
+    end.record()
+    torch.cuda.synchronize()
+    ms_solo = start.elapsed_time(end)
+    value = dof * 3 * args.steps / (ms / 1e3)
+    alg_bytes = 32 * dof   # FP32: 8 + 12 + 12 bytes per DOF per step
+    line = {
+        "metric": "phase-space DOF-updates/sec per RK stage (FP32) + % peak HBM BW",
+        "value": value, "unit": "DOF-updates/s per RK stage", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "uneven_sweep_64", "runs": len(wls), "dof": dof, "storage": "f32",
+                   "reductions": "f64", "parallelism": "single GPU, one persistent launch per stage"},
+        "hbm_effective_frac_whole_step": alg_bytes * args.steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "solo_sequential": {"ms_per_step": ms_solo / args.steps,
+                            "value": dof * 3 * args.steps / (ms_solo / 1e3)},
+        "batch_speedup_vs_solo": ms_solo / ms,
+        "tune": {"grid": b.grid, "best_ms_per_step": tuned_ms},
+    }
+    print(json.dumps(line), flush=True)
+    b.close()
+    for so in solos:
+        so.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +177,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the x-slab sharding is a design note); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "uneven_sweep_64":
+        return bench_sweep(args)
 
     import torch
     from paper_2202_13532_amd import dg

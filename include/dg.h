@@ -180,6 +180,75 @@ int32_t dg_batch_grid(const dg_batch* b);
 
 const char* dg_batch_last_error(const dg_batch* b);
 
+/* ---------- learned coarse-grid correction ----------------------------------
+ * A per-element multilayer perceptron corrects the RHS of a coarse 1D2V grid:
+ * for every coarse element its input row holds the element's n^3 nodal values,
+ * the six face neighbours' n^3 blocks (periodic) and E at its n x nodes
+ * (7 n^3 + n features), normalised per feature; the output is an n^3 RHS
+ * correction.  Layers are Linear with exact GELU after all but the last;
+ * matrix products run on BF16 MFMA with FP32 accumulation, parameters are
+ * FP32 masters with BF16 copies, training uses MSE and AdamW.  Fine-grid DG
+ * runs generate the training data: f and RHS are L2-projected to the coarse
+ * grid and the target is P RHS_fine(f) - RHS_coarse(P f).                  */
+
+typedef struct dg_nn dg_nn;
+
+/* sizes[0..nlayers]: input width, hidden widths..., output width.  Buffers
+ * for up to max_rows rows.                                                  */
+size_t dg_nn_workspace_bytes(const int32_t* sizes, int32_t nlayers, int32_t max_rows);
+dg_status dg_nn_init(const int32_t* sizes, int32_t nlayers, int32_t max_rows, void* workspace,
+                     size_t workspace_bytes, void* hip_stream, dg_nn** out);
+dg_status dg_nn_destroy(dg_nn* nn);
+int64_t dg_nn_param_count(const dg_nn* nn);
+/* Padded row stride (BF16 elements, multiple of 16) of the input rows X.   */
+int32_t dg_nn_input_ld(const dg_nn* nn);
+/* Host parameter vector: W_0 (in x out, row-major), b_0, W_1, b_1, ...     */
+dg_status dg_nn_set_params(dg_nn* nn, const float* host_params);
+dg_status dg_nn_get_params(dg_nn* nn, float* host_params);
+/* Y (device, rows x out FP32) = network(X) for X (device, rows x input_ld
+ * BF16); rows <= max_rows.                                                 */
+dg_status dg_nn_forward(dg_nn* nn, const uint16_t* X, int32_t rows, float* Y);
+/* Forward + backward of the MSE loss mean((Y - T)^2) for targets T (device,
+ * rows x out FP32); *loss receives the loss (host, waits); host_grads (may be
+ * NULL) receives the gradient in the parameter-vector order.               */
+dg_status dg_nn_loss_grad(dg_nn* nn, const uint16_t* X, const float* T, int32_t rows, double* loss, float* host_grads);
+/* One AdamW step (beta1 0.9, beta2 0.999, eps 1e-8) with the gradients of
+ * the last dg_nn_loss_grad; weight decay on weights only.                   */
+dg_status dg_nn_adamw(dg_nn* nn, float lr, float weight_decay);
+
+/* One-axis L2 projection matrix (host, FP64, row-major nc x r*nf) from the r
+ * fine elements with nf LGL nodes inside one coarse element with nc nodes:
+ * exact mass matrix and coupling integrals.  nc*r*nf <= 324.                */
+dg_status dg_projection_matrix(int32_t nc, int32_t nf, int32_t r, double* out);
+/* L2 projection of a fine FP32 state (1D1V or 1D2V) onto a nested coarse grid
+ * with the same domain (fine element counts multiples of the coarse ones),
+ * axis by axis with dg_projection_matrix, FP64 arithmetic, FP32 result.
+ * Uses the fine context's two stage buffers as scratch (each partial result
+ * must fit one of them, else DG_ERR_UNSUPPORTED).  Enqueued on the fine
+ * context's stream after both callers' streams; the coarse caller's stream
+ * waits for it.                                                             */
+dg_status dg_project(dg_ctx* fine, dg_ctx* coarse, const void* f_fine, void* f_coarse);
+/* Network input rows of a coarse FP32 state f with field E (device, Nx*n):
+ * (value - mean) * inv_std per feature (device arrays of 7 n^3 + n floats),
+ * BF16, one row per element, element order (ix, iu, iv).                   */
+dg_status dg_nn_features(dg_ctx* coarse, const dg_nn* nn, const void* f, const double* E, const float* mean,
+                         const float* inv_std, uint16_t* X);
+/* Raw (FP32, unnormalised) feature rows, elements x (7 n^3 + n).           */
+dg_status dg_nn_features_raw(dg_ctx* coarse, const void* f, const double* E, float* out);
+/* Element-major copy (elements x n^3) of scale * (x - sub) for coarse
+ * state-layout FP32 arrays x and sub (sub may be NULL: scale * x): the
+ * training target scale * (P RHS_fine - RHS_coarse(P f)).                  */
+dg_status dg_nn_to_elements(dg_ctx* coarse, const void* x, const void* sub, float scale, float* out);
+/* Per-column sums and sums of squares (host FP64) of a device FP32 matrix.  */
+dg_status dg_nn_column_stats(dg_nn* nn, const float* X, int64_t rows, int32_t cols, double* host_sum, double* host_sumsq);
+/* nsteps SSP-RK3 steps of the coarse grid with RHS L(u) + out_scale * NN(u)
+ * at every stage (the correction made mass neutral per element under the
+ * LGL product weights), Poisson from each corrected stage state.  f: coarse
+ * FP32 state in place.  host_diag as dg_rk_step.                            */
+dg_status dg_nn_rk_step(dg_ctx* coarse, dg_nn* nn, const float* mean, const float* inv_std, float out_scale,
+                        void* f, double dt, int32_t nsteps, dg_diag* host_diag);
+const char* dg_nn_last_error(const dg_nn* nn);
+
 /* ---------- host-only introspection of the FP64 setup (no device) -------- */
 
 /* Reference-element operators for n nodes (eq. quad_weights, eq. minv,

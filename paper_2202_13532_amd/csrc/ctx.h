@@ -55,6 +55,8 @@ dg_status stage(dg_ctx* c, const void* fin, const void* fun, void* out, const do
                 double c_un, double c_in, double c_dt);
 // Density partials of f (FP64) into the workspace.
 dg_status density(dg_ctx* c, const void* f);
+// Velocity moments of f into the diagnostics ring (after a recording field solve).
+dg_status moments(dg_ctx* c, const void* f);
 // Field solve from the workspace density partials.
 dg_status field(dg_ctx* c, double* E, double* coeffs, bool record);
 dg_status enter(dg_ctx* c);

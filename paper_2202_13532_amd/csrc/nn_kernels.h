@@ -1,0 +1,80 @@
+// Launch interface of the learned-correction kernels (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace dgn {
+
+constexpr int kMaxProj = 324;   // nc * r * nf entries of a projection matrix
+
+struct ProjArgs {
+  const void* in;     // [outer, Nc*r*nf, inner], FP32 if in_f32 else FP64
+  double* out;        // [outer, Nc*nc, inner]
+  double P[kMaxProj]; // nc x (r*nf), row-major
+  int outer, inner, Nc, nc, nf, r, in_f32;
+};
+
+struct GatherArgs {
+  const float* f;       // coarse state [Nx, n, Nu, n, Nv, n]
+  const double* E;      // Nx*n field
+  const float* mean;    // nfeat
+  const float* inv_std; // nfeat
+  uint16_t* X;          // rows x ld (BF16)
+  int Nx, Nu, Nv, n, nfeat, ld;
+};
+
+struct ScatterArgs {
+  const float* Y;       // rows x ldy network output (element-major)
+  float* out;           // state layout
+  float w[16];          // n reference LGL weights
+  float scale;
+  int Nx, Nu, Nv, n, ldy, mass_neutral;
+};
+
+struct GemmArgs {
+  const uint16_t* A;    // A(m,k) = A[m*sam + k*sak]
+  const uint16_t* B;    // B(k,n) = B[k*sbk + n*sbn]
+  float* C;             // C(m,n) = C[m*scm + n*scn]
+  size_t sam, sak, sbk, sbn, scm, scn;
+  int M, N, K;
+  float beta;
+};
+
+struct BiasActArgs {
+  const float* Y;       // rows x cols
+  const float* bias;    // cols or nullptr
+  float* Z;             // rows x cols pre-activation (or nullptr)
+  float* Af;            // rows x cols activation FP32 (or nullptr)
+  uint16_t* Abf;        // rows x ld activation BF16 (or nullptr)
+  int rows, cols, ld, gelu;
+};
+
+struct AdamArgs {
+  float* p;
+  const float* grad;
+  float* m;
+  float* v;
+  uint16_t* bf;         // BF16 copy (or nullptr)
+  size_t count;
+  float lr, b1, b2, eps, wd, c1, c2;   // c1 = 1 - b1^t, c2 = 1 - b2^t
+};
+
+hipError_t launch_project_axis(const ProjArgs& a, hipStream_t s);
+hipError_t launch_f32_to_f64(const float* in, double* out, size_t n, hipStream_t s);
+hipError_t launch_f64_to_f32(const double* in, float* out, size_t n, hipStream_t s);
+hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
+hipError_t launch_gather_raw(const GatherArgs& a, float* out, hipStream_t s);
+hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
+hipError_t launch_bias_act(const BiasActArgs& a, hipStream_t s);
+hipError_t launch_gelu_back(const float* dA, const float* Z, float* dZ, uint16_t* dZb, int rows, int cols, int ld, hipStream_t s);
+hipError_t launch_mse(const float* Y, const float* T, int rows, int cols, int ld, float inv_count, float* dY, uint16_t* dYb,
+                      double* partial, int nblocks, hipStream_t s);
+hipError_t launch_colsum(const float* in, int rows, int cols, float* out, hipStream_t s);
+hipError_t launch_adamw(const AdamArgs& a, hipStream_t s);
+hipError_t launch_colstats(const float* X, size_t rows, int ld, int cols, double* sum, double* sumsq, hipStream_t s);
+hipError_t launch_to_elements(const float* in, const float* sub, float scale, float* out, int n, int Nx, int Nu, int Nv, hipStream_t s);
+hipError_t launch_axpy(float* y, const float* x, float a, size_t n, hipStream_t s);
+
+}  // namespace dgn

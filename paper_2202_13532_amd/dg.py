@@ -21,7 +21,11 @@ STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_INVALID", 2: "DG_ERR_UNSUPPORTED", 3: "DG
 EXPORTED = ["dg_workspace_bytes", "dg_init", "dg_destroy", "dg_rhs", "dg_poisson", "dg_rk_step",
             "dg_diagnostics", "dg_profile_step", "dg_dt_max", "dg_node_coords", "dg_last_error", "dg_basis",
             "dg_connection_tensor", "dg_courant_number", "dg_batch_workspace_bytes", "dg_batch_init",
-            "dg_batch_destroy", "dg_batch_rk_step", "dg_batch_tune", "dg_batch_grid", "dg_batch_last_error"]
+            "dg_batch_destroy", "dg_batch_rk_step", "dg_batch_tune", "dg_batch_grid", "dg_batch_last_error",
+            "dg_nn_workspace_bytes", "dg_nn_init", "dg_nn_destroy", "dg_nn_param_count", "dg_nn_input_ld",
+            "dg_nn_set_params", "dg_nn_get_params", "dg_nn_forward", "dg_nn_loss_grad", "dg_nn_adamw",
+            "dg_projection_matrix", "dg_project", "dg_nn_features", "dg_nn_features_raw", "dg_nn_to_elements",
+            "dg_nn_column_stats", "dg_nn_rk_step", "dg_nn_last_error"]
 
 
 class dg_config(ctypes.Structure):
@@ -61,6 +65,8 @@ def lib():
     cfgp = ctypes.POINTER(dg_config)
     diagp = ctypes.POINTER(dg_diag)
     dp = ctypes.POINTER(ctypes.c_double)
+    fp = ctypes.POINTER(ctypes.c_float)
+    ip = ctypes.POINTER(ctypes.c_int32)
     sig = {
         "dg_workspace_bytes": (S, [cfgp]),
         "dg_init": (I, [cfgp, P, S, P, ctypes.POINTER(P)]),
@@ -83,6 +89,24 @@ def lib():
         "dg_batch_tune": (I, [P, ctypes.POINTER(P), dp, I, dp]),
         "dg_batch_grid": (I, [P]),
         "dg_batch_last_error": (ctypes.c_char_p, [P]),
+        "dg_nn_workspace_bytes": (S, [ip, I, I]),
+        "dg_nn_init": (I, [ip, I, I, P, S, P, ctypes.POINTER(P)]),
+        "dg_nn_destroy": (I, [P]),
+        "dg_nn_param_count": (ctypes.c_int64, [P]),
+        "dg_nn_input_ld": (I, [P]),
+        "dg_nn_set_params": (I, [P, fp]),
+        "dg_nn_get_params": (I, [P, fp]),
+        "dg_nn_forward": (I, [P, P, I, P]),
+        "dg_nn_loss_grad": (I, [P, P, P, I, dp, fp]),
+        "dg_nn_adamw": (I, [P, ctypes.c_float, ctypes.c_float]),
+        "dg_projection_matrix": (I, [I, I, I, dp]),
+        "dg_project": (I, [P, P, P, P]),
+        "dg_nn_features": (I, [P, P, P, P, P, P, P]),
+        "dg_nn_features_raw": (I, [P, P, P, P]),
+        "dg_nn_to_elements": (I, [P, P, P, ctypes.c_float, P]),
+        "dg_nn_column_stats": (I, [P, P, ctypes.c_int64, I, dp, dp]),
+        "dg_nn_rk_step": (I, [P, P, P, P, ctypes.c_float, P, D, I, diagp]),
+        "dg_nn_last_error": (ctypes.c_char_p, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -375,3 +399,184 @@ class Batch:
     @property
     def grid(self):
         return dg_batch_grid(self.b)
+
+
+# ---------------- learned coarse-grid correction ----------------
+
+def _ncheck(status, nn=None):
+    if status != DG_OK:
+        raise DGError(status, lib().dg_nn_last_error(nn).decode())
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _sizes(sizes):
+    return (ctypes.c_int32 * len(sizes))(*[int(x) for x in sizes])
+
+
+def dg_nn_workspace_bytes(sizes, max_rows):
+    return int(lib().dg_nn_workspace_bytes(_sizes(sizes), len(sizes) - 1, int(max_rows)))
+
+
+def dg_nn_init(sizes, max_rows, workspace, stream=None):
+    nn = ctypes.c_void_p()
+    st = lib().dg_nn_init(_sizes(sizes), len(sizes) - 1, int(max_rows), _ptr(workspace),
+                          workspace.numel() * workspace.element_size(), ctypes.c_void_p(stream), ctypes.byref(nn))
+    _ncheck(st, None)
+    return nn
+
+
+def dg_nn_destroy(nn):
+    _ncheck(lib().dg_nn_destroy(nn), None)
+
+
+def dg_nn_param_count(nn):
+    return int(lib().dg_nn_param_count(nn))
+
+
+def dg_nn_input_ld(nn):
+    return int(lib().dg_nn_input_ld(nn))
+
+
+def dg_nn_set_params(nn, params):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _ncheck(lib().dg_nn_set_params(nn, _fptr(a)), nn)
+
+
+def dg_nn_get_params(nn):
+    a = np.zeros(dg_nn_param_count(nn), dtype=np.float32)
+    _ncheck(lib().dg_nn_get_params(nn, _fptr(a)), nn)
+    return a
+
+
+def dg_nn_forward(nn, X, rows, Y):
+    _ncheck(lib().dg_nn_forward(nn, _ptr(X), int(rows), _ptr(Y)), nn)
+
+
+def dg_nn_loss_grad(nn, X, T, rows, want_loss=True, want_grads=False):
+    loss = np.zeros(1)
+    g = np.zeros(dg_nn_param_count(nn), dtype=np.float32) if want_grads else None
+    _ncheck(lib().dg_nn_loss_grad(nn, _ptr(X), _ptr(T), int(rows), _dptr(loss) if want_loss else None,
+                                  _fptr(g) if want_grads else None), nn)
+    return (float(loss[0]) if want_loss else None), g
+
+
+def dg_nn_adamw(nn, lr, weight_decay=0.0):
+    _ncheck(lib().dg_nn_adamw(nn, float(lr), float(weight_decay)), nn)
+
+
+def dg_nn_column_stats(nn, X, rows, cols):
+    s, q = np.zeros(cols), np.zeros(cols)
+    _ncheck(lib().dg_nn_column_stats(nn, _ptr(X), int(rows), int(cols), _dptr(s), _dptr(q)), nn)
+    return s, q
+
+
+def dg_nn_last_error(nn=None):
+    return lib().dg_nn_last_error(nn).decode()
+
+
+def dg_projection_matrix(nc, nf, r):
+    out = np.zeros(nc * r * nf)
+    _check(lib().dg_projection_matrix(int(nc), int(nf), int(r), _dptr(out)))
+    return out.reshape(nc, r * nf)
+
+
+def dg_project(fine_ctx, coarse_ctx, f_fine, f_coarse):
+    _check(lib().dg_project(fine_ctx, coarse_ctx, _ptr(f_fine), _ptr(f_coarse)), coarse_ctx)
+
+
+def dg_nn_features(coarse_ctx, nn, f, E, mean, inv_std, X):
+    _check(lib().dg_nn_features(coarse_ctx, nn, _ptr(f), _ptr(E), _ptr(mean), _ptr(inv_std), _ptr(X)), coarse_ctx)
+
+
+def dg_nn_features_raw(coarse_ctx, f, E, out):
+    _check(lib().dg_nn_features_raw(coarse_ctx, _ptr(f), _ptr(E), _ptr(out)), coarse_ctx)
+
+
+def dg_nn_to_elements(coarse_ctx, x, sub, scale, out):
+    _check(lib().dg_nn_to_elements(coarse_ctx, _ptr(x), _ptr(sub), float(scale), _ptr(out)), coarse_ctx)
+
+
+def dg_nn_rk_step(coarse_ctx, nn, mean, inv_std, out_scale, f, dt, nsteps, diag=False):
+    recs = (dg_diag * nsteps)() if (diag and nsteps > 0) else None
+    st = lib().dg_nn_rk_step(coarse_ctx, nn, _ptr(mean), _ptr(inv_std), float(out_scale), _ptr(f), float(dt),
+                             int(nsteps), recs)
+    _check(st, coarse_ctx)
+    return [r.as_dict() for r in recs] if recs is not None else None
+
+
+class Network:
+    """Per-element MLP of the learned correction; owns its device workspace."""
+
+    def __init__(self, sizes, max_rows, device="cuda"):
+        import torch
+        self.torch = torch
+        self.sizes = [int(x) for x in sizes]
+        self.max_rows = int(max_rows)
+        nbytes = dg_nn_workspace_bytes(self.sizes, self.max_rows)
+        if nbytes == 0:
+            raise DGError(DG_ERR_INVALID, "invalid network configuration")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws = self.workspace[off:off + nbytes]
+        self.nn = dg_nn_init(self.sizes, self.max_rows, self.ws, torch.cuda.current_stream(self.device).cuda_stream)
+        self.ld = dg_nn_input_ld(self.nn)
+        self.nparam = dg_nn_param_count(self.nn)
+
+    def close(self):
+        if getattr(self, "nn", None) is not None:
+            dg_nn_destroy(self.nn)
+            self.nn = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        dg_nn_set_params(self.nn, flat)
+
+    def get_params(self):
+        return dg_nn_get_params(self.nn)
+
+    def unflatten(self, flat):
+        out, o = [], 0
+        for a, b in zip(self.sizes[:-1], self.sizes[1:]):
+            out.append(np.asarray(flat[o:o + a * b]).reshape(a, b))
+            o += a * b
+            out.append(np.asarray(flat[o:o + b]))
+            o += b
+        return out
+
+    @staticmethod
+    def flatten(params):
+        return np.concatenate([np.asarray(p, dtype=np.float32).ravel() for p in params])
+
+    def _rows(self, X):
+        t = self.torch
+        if X.dtype != t.int16 or X.dim() != 2 or X.shape[1] != self.ld or not X.is_contiguous():
+            raise DGError(DG_ERR_INVALID, "X must be contiguous int16 (BF16 bits) of shape (rows, %d)" % self.ld)
+        return X.shape[0]
+
+    def forward(self, X, out=None):
+        rows = self._rows(X)
+        Y = self.torch.empty((rows, self.sizes[-1]), dtype=self.torch.float32, device=self.device) if out is None else out
+        dg_nn_forward(self.nn, X, rows, Y)
+        return Y
+
+    def loss_grad(self, X, T, want_loss=True, want_grads=False):
+        rows = self._rows(X)
+        if T.dtype != self.torch.float32 or tuple(T.shape) != (rows, self.sizes[-1]) or not T.is_contiguous():
+            raise DGError(DG_ERR_INVALID, "T must be contiguous float32 of shape (rows, %d)" % self.sizes[-1])
+        return dg_nn_loss_grad(self.nn, X, T, rows, want_loss, want_grads)
+
+    def adamw(self, lr, weight_decay=0.0):
+        dg_nn_adamw(self.nn, lr, weight_decay)
+
+    def column_stats(self, X):
+        rows, cols = X.shape
+        return dg_nn_column_stats(self.nn, X, rows, cols)

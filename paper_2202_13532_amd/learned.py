@@ -1,0 +1,347 @@
+"""Learned coarse-grid correction: data from fine DG runs, training, corrected runs.
+
+Orchestration only.  Every numerical step runs in libdg through the C ABI:
+fine and coarse SSP-RK3 steps, the fine -> coarse L2 projection, both RHS
+evaluations, the target difference, the feature gather and normalisation,
+the BF16-MFMA network forward / backward, AdamW and the corrected coarse
+steps.  Host code draws seeds, orders minibatches and turns the per-column
+sums returned by the library into normalisation constants.
+
+Setting (1D2V, x in [0, 4 pi), v in [-8, 8]^2, omega_c = 1, FP32 storage):
+  fine    32^3 elements, n = 8 (16 777 216 DOF)
+  coarse  16^3 elements, n = 4 (262 144 DOF, 4096 elements)
+  network 452 -> 128 -> 128 -> 128 -> 64 (exact GELU), 99 264 parameters
+Per run r (seed s): a ~ U[0, 1], v_t ~ U[0.7, 1.3] from default_rng(s);
+f0 = a ring(r0 = 3) + (1 - a) Maxwellian(v_t), times 1 + 1e-3 cos(0.5 x).
+A training snapshot of fine state f gives the coarse input P f and the target
+P RHS_fine(f) - RHS_coarse(P f) (per coarse element, n^3 values).
+"""
+import math
+import time
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+from . import dg, inputs
+
+LO = [0.0, -8.0, -8.0]
+HI = [4.0 * math.pi, 8.0, 8.0]
+OMEGA_C = 1.0
+
+
+@dataclass
+class Config:
+    n_fine: int = 8
+    nelem_fine: int = 32
+    n_coarse: int = 4
+    nelem_coarse: int = 16
+    hidden: List[int] = field(default_factory=lambda: [128, 128, 128])
+    train_seeds: List[int] = field(default_factory=lambda: list(range(32)))
+    snapshots_per_run: int = 64
+    snapshot_stride: int = 16          # fine steps between snapshots
+    spinup_steps: int = 0              # fine steps before the first snapshot
+    epochs: int = 3
+    lr: float = 1e-3
+    weight_decay: float = 1e-4
+    init_seed: int = 12345
+    cfl_fraction: float = 0.9
+
+
+def run_parameters(seed):
+    g = np.random.default_rng(seed)
+    return {"a": float(g.uniform(0.0, 1.0)), "vt": float(g.uniform(0.7, 1.3))}
+
+
+class LearnedCorrection:
+    """Fine and coarse solvers, the network and its normalisation."""
+
+    def __init__(self, cfg=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.cfg = cfg or Config()
+        c = self.cfg
+        self.fine = dg.Solver(2, c.n_fine, [c.nelem_fine] * 3, LO, HI, OMEGA_C, device=device)
+        self.coarse = dg.Solver(2, c.n_coarse, [c.nelem_coarse] * 3, LO, HI, OMEGA_C, device=device)
+        n = c.n_coarse
+        self.nb = n ** 3
+        self.nfeat = 7 * self.nb + n
+        self.ne = c.nelem_coarse ** 3
+        self.sizes = [self.nfeat] + list(c.hidden) + [self.nb]
+        self.net = dg.Network(self.sizes, self.ne)
+        self.device = self.fine.device
+        self.mean = None
+        self.inv_std = None
+        self.target_scale = 1.0
+
+    # ---------------- states ----------------
+    def initial_fine_state(self, seed):
+        t = self.torch
+        p = run_parameters(seed)
+        nodes = [t.from_numpy(self.fine.nodes(a)).to(self.device) for a in range(3)]
+        x, u, v = inputs.broadcast_coords(nodes, t)
+        f = inputs.mixture(x, u, v, p["a"], p["vt"], 0.5, 1e-3, 3.0, t)
+        return f.to(t.float32).contiguous()
+
+    def project(self, f_fine, out=None):
+        out = self.coarse.empty_state() if out is None else out
+        dg.dg_project(self.fine.ctx, self.coarse.ctx, f_fine, out)
+        return out
+
+    def fine_dt(self, f):
+        E = self.fine.poisson(f)
+        return self.cfg.cfl_fraction * self.fine.dt_max(float(E.abs().max()))
+
+    def coarse_dt(self, fc):
+        E = self.coarse.poisson(fc)
+        return self.cfg.cfl_fraction * self.coarse.dt_max(float(E.abs().max()))
+
+    # ---------------- data ----------------
+    def snapshot(self, f):
+        """(coarse state P f, its field, P RHS_f(f), RHS_c(P f)), all coarse state layout."""
+        fc = self.project(f)
+        rf = self.fine.rhs(f)
+        prf = self.project(rf)
+        rc = self.coarse.rhs(fc)
+        E = self.coarse.poisson(fc)
+        return fc, E, (prf, rc)
+
+    def targets(self, pair, scale=1.0, out=None):
+        """Element-major target scale * (P RHS_f(f) - RHS_c(P f))."""
+        t = self.torch
+        out = t.empty((self.ne, self.nb), dtype=t.float32, device=self.device) if out is None else out
+        dg.dg_nn_to_elements(self.coarse.ctx, pair[0], pair[1], float(scale), out)
+        return out
+
+    def generate(self, seeds, nsnap=None, stride=None, log=None):
+        """Snapshots of fine runs: lists of coarse states, fields and targets."""
+        c = self.cfg
+        nsnap = c.snapshots_per_run if nsnap is None else nsnap
+        stride = c.snapshot_stride if stride is None else stride
+        states, fields, targets = [], [], []
+        for s in seeds:
+            f = self.initial_fine_state(s)
+            dt = self.fine_dt(f)
+            if c.spinup_steps:
+                self.fine.step(f, dt, c.spinup_steps)
+            for k in range(nsnap):
+                fc, E, tg = self.snapshot(f)
+                states.append(fc)
+                fields.append(E)
+                targets.append(tg)
+                if k + 1 < nsnap:
+                    self.fine.step(f, dt, stride)
+            if log:
+                log("run seed %d: %d snapshots, dt_fine %.3e" % (s, nsnap, dt))
+        return states, fields, targets
+
+    def fit_normalisation(self, states, fields, targets):
+        t = self.torch
+        raw = t.empty((self.ne, self.nfeat), dtype=t.float32, device=self.device)
+        s1 = np.zeros(self.nfeat)
+        s2 = np.zeros(self.nfeat)
+        for fc, E in zip(states, fields):
+            dg.dg_nn_features_raw(self.coarse.ctx, fc, E, raw)
+            a, b = self.net.column_stats(raw)
+            s1 += a
+            s2 += b
+        cnt = float(self.ne * len(states))
+        mean = s1 / cnt
+        var = np.maximum(s2 / cnt - mean * mean, 0.0)
+        std = np.sqrt(var)
+        # features that barely vary (e.g. far velocity tails) are not amplified
+        floor = 1e-3 * max(float(np.max(std)), 1e-30)
+        self.mean = t.from_numpy(mean.astype(np.float32)).to(self.device)
+        self.inv_std = t.from_numpy((1.0 / np.maximum(std, floor)).astype(np.float32)).to(self.device)
+        tsq = 0.0
+        tg = t.empty((self.ne, self.nb), dtype=t.float32, device=self.device)
+        for pair in targets:
+            a, b = self.net.column_stats(self.targets(pair, 1.0, tg))
+            tsq += float(np.sum(b))
+        self.target_scale = math.sqrt(tsq / (cnt * self.nb)) if tsq > 0 else 1.0
+
+    def features(self, fc, E, out=None):
+        t = self.torch
+        X = t.empty((self.ne, self.net.ld), dtype=t.int16, device=self.device) if out is None else out
+        dg.dg_nn_features(self.coarse.ctx, self.net.nn, fc, E, self.mean, self.inv_std, X)
+        return X
+
+    def dataset(self, states, fields, targets):
+        """Stacked BF16 feature rows and normalised FP32 targets (one block of
+        ne rows per snapshot)."""
+        t = self.torch
+        ns = len(states)
+        X = t.empty((ns, self.ne, self.net.ld), dtype=t.int16, device=self.device)
+        T = t.empty((ns, self.ne, self.nb), dtype=t.float32, device=self.device)
+        for i, (fc, E, pair) in enumerate(zip(states, fields, targets)):
+            self.features(fc, E, X[i])
+            self.targets(pair, 1.0 / self.target_scale, T[i])
+        return X, T
+
+    # ---------------- training ----------------
+    def init_params(self, seed=None):
+        rng = np.random.default_rng(self.cfg.init_seed if seed is None else seed)
+        ps = []
+        for a, b in zip(self.sizes[:-1], self.sizes[1:]):
+            ps.append(rng.standard_normal((a, b)) * math.sqrt(2.0 / a))
+            ps.append(np.zeros(b))
+        # the last layer starts small: the untrained correction is near zero
+        ps[-2] *= 0.01
+        self.net.set_params(dg.Network.flatten(ps))
+
+    def train(self, X, T, epochs=None, lr=None, seed=0, log=None, log_every=200):
+        c = self.cfg
+        epochs = c.epochs if epochs is None else epochs
+        lr0 = c.lr if lr is None else lr
+        ns = X.shape[0]
+        total = epochs * ns
+        rng = np.random.default_rng(seed)
+        history = []
+        step = 0
+        for ep in range(epochs):
+            for i in rng.permutation(ns):
+                lr_t = 0.5 * lr0 * (1.0 + math.cos(math.pi * step / max(total, 1)))
+                want = (step % log_every == 0) or step == total - 1
+                loss, _ = self.net.loss_grad(X[i], T[i], want_loss=want)
+                self.net.adamw(lr_t, c.weight_decay)
+                if want:
+                    history.append((step, loss))
+                    if log:
+                        log("step %d epoch %d loss %.5f lr %.2e" % (step, ep, loss, lr_t))
+                step += 1
+        return history
+
+    def relative_error(self, X, T):
+        """||T - NN(X)|| / ||T|| over the given snapshots (normalised units)."""
+        num = den = 0.0
+        for i in range(X.shape[0]):
+            Y = self.net.forward(X[i])
+            num += float(((Y - T[i]) ** 2).sum())
+            den += float((T[i] ** 2).sum())
+        return math.sqrt(num / den)
+
+    # ---------------- corrected runs ----------------
+    def run_coarse(self, fc, dt, nsteps, corrected):
+        if corrected:
+            return dg.dg_nn_rk_step(self.coarse.ctx, self.net.nn, self.mean, self.inv_std, self.target_scale, fc,
+                                    dt, nsteps, diag=True)
+        return self.coarse.step(fc, dt, nsteps, diag=True)
+
+    def evaluate(self, seed, coarse_steps, log=None):
+        """Field-energy histories of the fine run, the plain coarse run and the
+        corrected coarse run from the same initial state, compared at the
+        coarse step times (fine history interpolated linearly in time)."""
+        f = self.initial_fine_state(seed)
+        fc0 = self.project(f)
+        dtc = self.coarse_dt(fc0)
+        dtf = self.fine_dt(f)
+        tend = coarse_steps * dtc
+        nf = int(math.ceil(tend / dtf))
+        dtf = tend / nf
+        f0_energy = self.fine.diagnostics(f)["field_energy"]
+        t0 = time.perf_counter()
+        fine = self.fine.step(f, dtf, nf, diag=True)
+        t_fine = time.perf_counter() - t0
+        tf = np.concatenate([[0.0], np.arange(1, nf + 1) * dtf])
+        wf = np.concatenate([[f0_energy], [d["field_energy"] for d in fine]])
+        a = fc0.clone()
+        b = fc0.clone()
+        t0 = time.perf_counter()
+        plain = self.run_coarse(a, dtc, coarse_steps, False)
+        t_plain = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        corr = self.run_coarse(b, dtc, coarse_steps, True)
+        t_corr = time.perf_counter() - t0
+        tc = np.arange(1, coarse_steps + 1) * dtc
+        ref = np.interp(tc, tf, wf)
+        wp = np.array([d["field_energy"] for d in plain])
+        wc = np.array([d["field_energy"] for d in corr])
+
+        def rel(w):
+            return float(np.linalg.norm(w - ref) / np.linalg.norm(ref))
+
+        def relmax(w):
+            return float(np.max(np.abs(w - ref) / np.abs(ref)))
+
+        out = {
+            "seed": seed, "coarse_steps": coarse_steps, "dt_coarse": dtc, "fine_steps": nf, "dt_fine": dtf,
+            "t_end": tend,
+            "field_energy_rel_l2": {"plain_coarse": rel(wp), "coarse_nn": rel(wc)},
+            "field_energy_rel_max": {"plain_coarse": relmax(wp), "coarse_nn": relmax(wc)},
+            "mass_drift": {"plain_coarse": abs(plain[-1]["mass"] - plain[0]["mass"]) / plain[0]["mass"],
+                           "coarse_nn": abs(corr[-1]["mass"] - corr[0]["mass"]) / corr[0]["mass"]},
+            "wall_s": {"fine": t_fine, "plain_coarse": t_plain, "coarse_nn": t_corr},
+            "dof_updates_per_sim_time": {
+                "fine": self.fine_dof() * 3 / dtf,
+                "coarse": self.coarse_dof() * 3 / dtc,
+            },
+            "history": {"t": tc.tolist(), "fine": ref.tolist(), "plain": wp.tolist(), "nn": wc.tolist()},
+        }
+        if log:
+            log("eval seed %d: rel L2 plain %.4f nn %.4f" % (seed, out["field_energy_rel_l2"]["plain_coarse"],
+                                                            out["field_energy_rel_l2"]["coarse_nn"]))
+        return out
+
+    def fine_dof(self):
+        return (self.cfg.nelem_fine * self.cfg.n_fine) ** 3
+
+    def coarse_dof(self):
+        return (self.cfg.nelem_coarse * self.cfg.n_coarse) ** 3
+
+    def close(self):
+        for o in (self.net, self.fine, self.coarse):
+            o.close()
+
+
+def main(argv=None):
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="train and evaluate the learned coarse-grid correction")
+    ap.add_argument("--runs", type=int, default=32)
+    ap.add_argument("--snapshots", type=int, default=64)
+    ap.add_argument("--stride", type=int, default=16)
+    ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--eval-seeds", type=int, nargs="*", default=[1000, 1001])
+    ap.add_argument("--coarse-steps", type=int, default=2000)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    cfg = Config(train_seeds=list(range(a.runs)), snapshots_per_run=a.snapshots, snapshot_stride=a.stride,
+                 epochs=a.epochs)
+    log = lambda m: print(m, flush=True)  # noqa: E731
+    lc = LearnedCorrection(cfg)
+    t0 = time.perf_counter()
+    st, fl, tg = lc.generate(cfg.train_seeds, log=log)
+    t_gen = time.perf_counter() - t0
+    lc.fit_normalisation(st, fl, tg)
+    X, T = lc.dataset(st, fl, tg)
+    del st, fl, tg
+    nval = max(1, X.shape[0] // 16)
+    lc.init_params()
+    err0 = lc.relative_error(X[-nval:], T[-nval:])
+    t0 = time.perf_counter()
+    hist = lc.train(X[:-nval], T[:-nval], log=log)
+    lc.torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    err1 = lc.relative_error(X[-nval:], T[-nval:])
+    # held-out runs: one-step closure error and field-energy histories
+    hs, hf, ht = lc.generate(a.eval_seeds, nsnap=8)
+    Xh, Th = lc.dataset(hs, hf, ht)
+    err_h = lc.relative_error(Xh, Th)
+    evals = [lc.evaluate(s, a.coarse_steps, log=log) for s in a.eval_seeds]
+    rep = {
+        "training": {"runs": a.runs, "snapshots": int(X.shape[0]), "rows": int(X.shape[0] * lc.ne),
+                     "generate_s": t_gen, "train_s": t_train, "loss_history": hist,
+                     "target_scale": lc.target_scale,
+                     "val_rel_err_untrained": err0, "val_rel_err_trained": err1,
+                     "heldout_rel_err_trained": err_h},
+        "evaluation": [{k: v for k, v in e.items() if k != "history"} for e in evals],
+    }
+    print(json.dumps(rep), flush=True)
+    if a.out:
+        with open(a.out, "w") as fh:
+            json.dump({"report": rep, "histories": [e["history"] for e in evals]}, fh)
+    lc.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -100,3 +100,32 @@ def test_init_rejects_bad_arguments_before_touching_a_device():
     assert dg.lib().dg_rhs(None, None, None, None) == dg.DG_ERR_INVALID
     assert dg.lib().dg_rk_step(None, None, 0.1, 1, None) == dg.DG_ERR_INVALID
     assert dg.lib().dg_dt_max(None, 0.0) == 0.0
+
+
+@pytest.mark.parametrize("nc,nf,r", [(4, 8, 2), (3, 5, 3), (4, 4, 1), (5, 3, 2), (9, 9, 4)])
+def test_host_projection_matrix_matches_oracle(nc, nf, r):
+    from oracle import projection
+    P = dg.dg_projection_matrix(nc, nf, r)
+    Po = projection.projection_matrix(nc, nf, r)
+    assert np.max(np.abs(P - Po)) < 1e-12 * max(1.0, np.max(np.abs(Po)))
+
+
+def test_projection_matrix_rejects_oversized():
+    out = np.zeros(1000)
+    assert dg.lib().dg_projection_matrix(9, 9, 5, out.ctypes.data_as(dg.ctypes.POINTER(dg.ctypes.c_double))) == dg.DG_ERR_INVALID
+
+
+def test_network_workspace_and_init_validation():
+    sizes = [452, 128, 128, 128, 64]
+    nb = dg.dg_nn_workspace_bytes(sizes, 4096)
+    # parameters: 452*128+128 + 2*(128*128+128) + 128*64+64 = 99 264
+    assert nb > 99264 * (4 + 2 + 4 + 4 + 4)
+    assert dg.dg_nn_workspace_bytes([452, 0, 64], 10) == 0
+    assert dg.dg_nn_workspace_bytes(sizes, 0) == 0
+    L = dg.lib()
+    arr = (dg.ctypes.c_int32 * 5)(*sizes)
+    out = dg.ctypes.c_void_p()
+    assert L.dg_nn_init(arr, 4, 4096, None, nb, None, dg.ctypes.byref(out)) == dg.DG_ERR_INVALID
+    assert "workspace" in dg.dg_nn_last_error(None)
+    assert L.dg_nn_init(arr, 0, 4096, None, nb, None, dg.ctypes.byref(out)) == dg.DG_ERR_INVALID
+    assert L.dg_nn_param_count(None) == 0

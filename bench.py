@@ -172,6 +172,8 @@ def main():
     ap.add_argument("--storage", default=None, help="override storage (f32/f64)")
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run two plain device copies of one state buffer (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -219,6 +221,12 @@ def main():
     tot_bytes = sum(bytes_per_launch) * prof.shape[0]
     achieved = tot_bytes / (st_ms.sum() / 1e3) / 1e9
     traffic = load_traffic(wl.name + "_" + wl.storage)
+    if args.copy_calibration:
+        buf = torch.empty_like(f)
+        for _ in range(2):
+            buf.copy_(f)
+        torch.cuda.synchronize()
+        del buf
     diag = s.diagnostics(f)
     line = {
         "metric": "phase-space DOF-updates/sec per RK stage (FP32) + % peak HBM BW",

@@ -154,28 +154,31 @@ typedef struct dg_batch dg_batch;
  * any nv / n / sizes).  0 if any configuration is invalid or not FP32.      */
 size_t dg_batch_workspace_bytes(const dg_config* cfgs, int32_t nruns);
 
-/* Set up every run (as dg_init does) inside one workspace, build the (run,
- * tile) work list ordered by decreasing tile cost and split over the 8 XCDs,
- * and bind the batch to hip_stream.  cfgs is copied.                        */
+/* Set up every run (as dg_init does) inside one workspace, group the runs by
+ * kind (n, nv), build each kind's (run, tile) work list ordered by
+ * decreasing tile cost and split over the 8 XCDs, and bind the batch to
+ * hip_stream.  cfgs is copied.                                              */
 dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, size_t workspace_bytes,
                         void* hip_stream, dg_batch** out);
 dg_status dg_batch_destroy(dg_batch* b);
 
 /* Advance every run r by nsteps SSP-RK3 steps of its own dt[r] (host array)
- * on its state f[r] (host array of device pointers), all runs' stages in ONE
- * persistent launch per RK stage followed by one batched field launch pair,
- * replayed from a captured HIP graph.  CFL and finiteness checks per run as
+ * on its state f[r] (host array of device pointers): per RK stage one
+ * persistent launch per kind (n, nv) present, covering all runs of that kind,
+ * then one batched field launch pair for all runs, replayed from a captured
+ * HIP graph.  CFL and finiteness checks per run as
  * dg_rk_step.  host_diag: NULL or nruns*nsteps records, run-major
  * (record s of run r at host_diag[r*nsteps + s]); then the call waits.      */
 dg_status dg_batch_rk_step(dg_batch* b, void* const* f, const double* dt, int32_t nsteps, dg_diag* host_diag);
 
 /* Autotuner: time `reps` batched steps for each candidate persistent grid
- * (work-groups per CU from 1 to the occupancy limit) and work-list order,
- * keep the fastest for this batch, and return its mean step time in ms.
- * The states are advanced by the timed steps.                               */
+ * (work-groups per CU from 1 to each kind's occupancy limit) and work-list
+ * order (cost-sorted or run-interleaved), keep the fastest for this batch,
+ * and return its mean step time in ms.  The states are advanced by the timed
+ * steps.                                                                    */
 dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t reps, double* best_ms);
 
-/* Current persistent grid (work-groups) of the batched stage kernel.        */
+/* Current persistent grid: work-groups of all kinds' stage launches summed.  */
 int32_t dg_batch_grid(const dg_batch* b);
 
 const char* dg_batch_last_error(const dg_batch* b);

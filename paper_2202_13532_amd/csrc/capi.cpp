@@ -125,6 +125,26 @@ std::vector<double> axis_weights(const dgh::Basis& b, int N, double lo, double h
   return w;
 }
 
+// Stage coefficients in the storage precision.  A stage that reads u^n
+// computes out = fin + c_un (u^n - fin) + c_dt L(fin), i.e. the convex
+// combination c_un u^n + (1 - c_un) fin for the rounded c_un, so no rounded
+// pair (c_un, c_in) has to sum to one (FP32 1/3 + 2/3 is 1 + 3e-8, which
+// would grow the mass by that much every step).  c_dt is (1 - c_un) dt for
+// the rounded c_un; c_in is stored as 1 - c_un.  Without u^n, c_in is 0 (RHS
+// only) or 1 and is applied as given.
+template <typename T>
+void store_coefficients(double c_un, double c_in, double c_dt, T* cu, T* ci, T* cd) {
+  *cu = static_cast<T>(c_un);
+  if (c_un != 0.0 && c_in > 0.0) {
+    const double in_rounded = 1.0 - static_cast<double>(*cu);
+    *ci = static_cast<T>(in_rounded);
+    *cd = static_cast<T>(c_dt / c_in * in_rounded);
+    return;
+  }
+  *ci = static_cast<T>(c_in);
+  *cd = static_cast<T>(c_dt);
+}
+
 template <typename T>
 void fill_pack(const dg_ctx* c, dgk::StageArgs<T>* p, const void* fin, const void* fun, void* out,
                const double* E, double* partials, double c_un, double c_in, double c_dt) {
@@ -158,9 +178,7 @@ void fill_pack(const dg_ctx* c, dgk::StageArgs<T>* p, const void* fin, const voi
     a.Jv = static_cast<T>(2.0 / c->dx[1]);
   }
   a.wc = static_cast<T>(c->cfg.omega_c);
-  a.c_un = static_cast<T>(c_un);
-  a.c_in = static_cast<T>(c_in);
-  a.c_dt = static_cast<T>(c_dt);
+  store_coefficients(c_un, c_in, c_dt, &a.c_un, &a.c_in, &a.c_dt);
 }
 
 // One fused stage kernel: out = c_un un + c_in fin + c_dt L(fin) (L with field E).
@@ -287,7 +305,7 @@ dg_status enqueue_step(dg_ctx* c, void* f, double dt, bool diag) {
 dg_status build_graph(dg_ctx* c, void* f, double dt, bool diag) {
   if (c->gexec && c->g_f == f && c->g_dt == dt && c->g_diag == diag) return DG_OK;
   if (c->gexec) {
-    hipGraphExecDestroy(c->gexec);
+    (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
   }
   DG_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -300,7 +318,7 @@ dg_status build_graph(dg_ctx* c, void* f, double dt, bool diag) {
   }
   if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
   e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
     c->gexec = nullptr;
     return hip_fail(c, e, "hipGraphInstantiate");
@@ -465,9 +483,9 @@ dg_status dg_destroy(dg_ctx* ctx) {
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
   if (ctx->owns_stream) {
-    hipEventDestroy(ctx->ev_in);
-    hipEventDestroy(ctx->ev_out);
-    hipStreamDestroy(ctx->stream);
+    (void)hipEventDestroy(ctx->ev_in);
+    (void)hipEventDestroy(ctx->ev_out);
+    (void)hipStreamDestroy(ctx->stream);
   }
   delete ctx;
   return e == hipSuccess ? DG_OK : DG_ERR_DEVICE;
@@ -694,13 +712,17 @@ struct dg_batch {
   char* ws = nullptr;
   // device tables
   dgk::StageArgs<float>* d_args = nullptr;   // 3 * nruns
-  int* d_kind = nullptr;
   int2* d_items = nullptr;
-  int* d_xcd = nullptr;
+  int* d_xcd = nullptr;                       // 9 per kind
   dgk::FieldArgs* d_fa = nullptr;             // 3 * nruns (record flag differs)
   int2* d_xitems = nullptr;
   int nitems = 0, nxitems = 0, max_pmax = 0;
-  int grid = 0, cus = 0, occ[2] = {0, 0};
+  // runs of one kind (n, nv): items [begin, begin + count) of the work list
+  struct Group {
+    int n, nv, begin, count, occ[2], grid;
+  };
+  std::vector<Group> groups;
+  int cus = 0, wmul = 0;                      // work-groups per CU of every launch (capped by occupancy)
   std::vector<int2> items_cost, items_rr;     // the two work-list orders
   int order = 0;                              // 0: cost-sorted, 1: run-interleaved
   hipGraphExec_t gexec = nullptr;
@@ -716,7 +738,7 @@ constexpr size_t kBatchTail = 1 << 16;
 
 struct BatchLayout {
   std::vector<size_t> run_off;
-  size_t args, kind, items, xcd, fa, xitems, total;
+  size_t args, items, xcd, fa, xitems, total;
 };
 
 BatchLayout batch_layout(const dg_config* cfgs, int nruns) {
@@ -732,9 +754,8 @@ BatchLayout batch_layout(const dg_config* cfgs, int nruns) {
   }
   auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
   B.args = take(3 * nruns * sizeof(dgk::StageArgs<float>));
-  B.kind = take(nruns * sizeof(int));
   B.items = take(static_cast<size_t>(ntiles) * sizeof(int2));
-  B.xcd = take(9 * sizeof(int));
+  B.xcd = take(9 * static_cast<size_t>(nruns) * sizeof(int));
   B.fa = take(3 * nruns * sizeof(dgk::FieldArgs));
   B.xitems = take(static_cast<size_t>(nx) * sizeof(int2));
   B.total = o;
@@ -769,6 +790,8 @@ std::vector<int> xcd_split(const std::vector<int2>& items, const std::vector<dou
   return begin;
 }
 
+// Work lists of the current order and their per-kind XCD splits; grids for
+// the current work-groups-per-CU multiplier.
 dg_status upload_items(dg_batch* b) {
   const std::vector<int2>& items = b->order == 0 ? b->items_cost : b->items_rr;
   std::vector<double> cost(b->nruns);
@@ -776,9 +799,17 @@ dg_status upload_items(dg_batch* b) {
     const Layout& L = b->runs[r]->L;
     cost[r] = static_cast<double>(L.dof) / L.ntiles;
   }
-  std::vector<int> xcd = xcd_split(items, cost);
+  std::vector<int> xcd;
+  for (auto& g : b->groups) {
+    std::vector<int2> part(items.begin() + g.begin, items.begin() + g.begin + g.count);
+    std::vector<int> x = xcd_split(part, cost);
+    xcd.insert(xcd.end(), x.begin(), x.end());
+    const int occ = std::max(1, std::min(g.occ[0], g.occ[1]));
+    // at least one work-group per XCD range (8), else a range would be skipped
+    g.grid = std::max(8, std::min(g.count, b->cus * std::min(b->wmul, occ)));
+  }
   DGB_HIP(b, hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
-  DGB_HIP(b, hipMemcpyAsync(b->d_xcd, xcd.data(), 9 * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  DGB_HIP(b, hipMemcpyAsync(b->d_xcd, xcd.data(), xcd.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
   DGB_HIP(b, hipStreamSynchronize(b->stream));
   return DG_OK;
 }
@@ -810,7 +841,11 @@ dg_status upload_args(dg_batch* b, void* const* f, const double* dt) {
 
 dg_status enqueue_batch_step(dg_batch* b, bool diag) {
   for (int k = 0; k < 3; ++k) {
-    DGB_HIP(b, dgk::launch_stage_batched(k > 0, b->d_args + k * b->nruns, b->d_kind, b->d_items, b->d_xcd, b->grid, b->stream));
+    for (size_t q = 0; q < b->groups.size(); ++q) {
+      const auto& g = b->groups[q];
+      DGB_HIP(b, dgk::launch_stage_batched(k > 0, g.n, g.nv, b->d_args + k * b->nruns, b->d_items + g.begin,
+                                           b->d_xcd + 9 * q, g.grid, b->stream));
+    }
     DGB_HIP(b, dgk::launch_field_batched(b->d_fa + k * b->nruns, b->d_xitems, b->nxitems, b->nruns, b->max_pmax, b->stream));
   }
   if (diag) {
@@ -828,7 +863,7 @@ dg_status build_batch_graph(dg_batch* b, void* const* f, const double* dt, bool 
   for (int r = 0; same && r < b->nruns; ++r) same = b->g_f[r] == f[r] && b->g_dt[r] == dt[r];
   if (same) return DG_OK;
   if (b->gexec) {
-    hipGraphExecDestroy(b->gexec);
+    (void)hipGraphExecDestroy(b->gexec);
     b->gexec = nullptr;
   }
   b->g_f.assign(f, f + b->nruns);
@@ -846,7 +881,7 @@ dg_status build_batch_graph(dg_batch* b, void* const* f, const double* dt, bool 
   }
   if (e != hipSuccess) return bfail(b, DG_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
   e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
     b->gexec = nullptr;
     return bfail(b, DG_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
@@ -950,28 +985,43 @@ dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, s
     b->runs.push_back(c);
   }
   b->d_args = reinterpret_cast<dgk::StageArgs<float>*>(b->ws + BL.args);
-  b->d_kind = reinterpret_cast<int*>(b->ws + BL.kind);
   b->d_items = reinterpret_cast<int2*>(b->ws + BL.items);
   b->d_xcd = reinterpret_cast<int*>(b->ws + BL.xcd);
   b->d_fa = reinterpret_cast<dgk::FieldArgs*>(b->ws + BL.fa);
   b->d_xitems = reinterpret_cast<int2*>(b->ws + BL.xitems);
-  // work lists: runs by decreasing tile cost, tiles in order (cost-sorted),
-  // or tiles of all runs interleaved round-robin (run-interleaved)
-  std::vector<int> kind(nruns), byc(nruns);
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if ((e = hipGetDevice(&dev)) != hipSuccess || (e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
+    return cleanup(DG_ERR_DEVICE, std::string("device query: ") + hipGetErrorString(e));
+  b->cus = prop.multiProcessorCount;
+  // Kinds in order of decreasing n.  Within a kind: runs by decreasing tile
+  // cost, tiles in order (cost-sorted), or the kind's runs' tiles interleaved
+  // round-robin (run-interleaved).
   std::vector<int2> xitems;
+  std::vector<int> kinds;
   for (int r = 0; r < nruns; ++r) {
-    kind[r] = 10 * cfgs[r].n + cfgs[r].nv;
-    byc[r] = r;
+    kinds.push_back(10 * cfgs[r].n + cfgs[r].nv);
     for (int ix = 0; ix < b->runs[r]->L.Nx; ++ix) xitems.push_back(make_int2(r, ix));
     b->max_pmax = std::max(b->max_pmax, b->runs[r]->L.pmax);
   }
-  std::stable_sort(byc.begin(), byc.end(), [&](int p, int q) {
-    const Layout &A = b->runs[p]->L, &B = b->runs[q]->L;
-    return static_cast<double>(A.dof) / A.ntiles > static_cast<double>(B.dof) / B.ntiles;
-  });
-  for (int r : byc)
-    for (int t = 0; t < b->runs[r]->L.ntiles; ++t) b->items_cost.push_back(make_int2(r, t));
-  {
+  std::vector<int> distinct(kinds);
+  std::sort(distinct.begin(), distinct.end(), [](int p, int q) { return p > q; });
+  distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+  int maxocc = 1;
+  for (int kd : distinct) {
+    dg_batch::Group g{};
+    g.n = kd / 10;
+    g.nv = kd % 10;
+    g.begin = static_cast<int>(b->items_cost.size());
+    std::vector<int> byc;
+    for (int r = 0; r < nruns; ++r)
+      if (kinds[r] == kd) byc.push_back(r);
+    std::stable_sort(byc.begin(), byc.end(), [&](int p, int q) {
+      const Layout &A = b->runs[p]->L, &B = b->runs[q]->L;
+      return static_cast<double>(A.dof) / A.ntiles > static_cast<double>(B.dof) / B.ntiles;
+    });
+    for (int r : byc)
+      for (int t = 0; t < b->runs[r]->L.ntiles; ++t) b->items_cost.push_back(make_int2(r, t));
     std::vector<int> next(nruns, 0);
     bool any = true;
     while (any) {
@@ -982,21 +1032,17 @@ dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, s
           any = true;
         }
     }
+    g.count = static_cast<int>(b->items_cost.size()) - g.begin;
+    g.occ[0] = dgk::batched_occupancy(false, g.n, g.nv);
+    g.occ[1] = dgk::batched_occupancy(true, g.n, g.nv);
+    maxocc = std::max(maxocc, std::min(g.occ[0], g.occ[1]));
+    b->groups.push_back(g);
   }
+  b->wmul = maxocc;
   b->nitems = static_cast<int>(b->items_cost.size());
   b->nxitems = static_cast<int>(xitems.size());
-  if ((e = hipMemcpyAsync(b->d_kind, kind.data(), nruns * sizeof(int), hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
-      (e = hipMemcpyAsync(b->d_xitems, xitems.data(), xitems.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream)) != hipSuccess)
+  if ((e = hipMemcpyAsync(b->d_xitems, xitems.data(), xitems.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream)) != hipSuccess)
     return cleanup(DG_ERR_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
-  int dev = 0;
-  hipDeviceProp_t prop;
-  if ((e = hipGetDevice(&dev)) != hipSuccess || (e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
-    return cleanup(DG_ERR_DEVICE, std::string("device query: ") + hipGetErrorString(e));
-  b->cus = prop.multiProcessorCount;
-  b->occ[0] = dgk::batched_occupancy(false);
-  b->occ[1] = dgk::batched_occupancy(true);
-  const int occ = std::max(1, std::min(b->occ[0], b->occ[1]));
-  b->grid = b->cus * occ;
   if (upload_items(b) != DG_OK) return cleanup(DG_ERR_DEVICE, b->err);
   *out = b;
   return DG_OK;
@@ -1007,9 +1053,9 @@ dg_status dg_batch_destroy(dg_batch* b) {
   hipError_t e = hipStreamSynchronize(b->stream);
   if (b->gexec) hipGraphExecDestroy(b->gexec);
   for (dg_ctx* c : b->runs) dg_destroy(c);
-  hipEventDestroy(b->ev_in);
-  hipEventDestroy(b->ev_out);
-  hipStreamDestroy(b->stream);
+  (void)hipEventDestroy(b->ev_in);
+  (void)hipEventDestroy(b->ev_out);
+  (void)hipStreamDestroy(b->stream);
   delete b;
   return e == hipSuccess ? DG_OK : DG_ERR_DEVICE;
 }
@@ -1069,16 +1115,18 @@ dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t r
   hipEvent_t e0, e1;
   DGB_HIP(b, hipEventCreate(&e0));
   DGB_HIP(b, hipEventCreate(&e1));
-  const int occ = std::max(1, std::min(b->occ[0], b->occ[1]));
+  int occ = 1;
+  for (const auto& g : b->groups) occ = std::max(occ, std::min(g.occ[0], g.occ[1]));
   double best = 1e300;
-  int best_grid = b->grid, best_order = b->order;
+  int best_w = b->wmul, best_order = b->order;
   for (int order = 0; order < 2 && s == DG_OK; ++order) {
     b->order = order;
-    s = upload_items(b);
     for (int w = 1; w <= occ && s == DG_OK; ++w) {
-      b->grid = b->cus * w;
+      b->wmul = w;
+      s = upload_items(b);
+      if (s != DG_OK) break;
       if (b->gexec) {
-        hipGraphExecDestroy(b->gexec);
+        (void)hipGraphExecDestroy(b->gexec);
         b->gexec = nullptr;
       }
       s = build_batch_graph(b, f, dt, false);
@@ -1092,28 +1140,33 @@ dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t r
       DGB_HIP(b, hipEventElapsedTime(&ms, e0, e1));
       if (ms / reps < best) {
         best = ms / reps;
-        best_grid = b->grid;
+        best_w = w;
         best_order = order;
       }
       for (int r = 0; r < b->nruns; ++r) b->runs[r]->t += (reps + 1) * dt[r];
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (s != DG_OK) return s;
-  b->grid = best_grid;
+  b->wmul = best_w;
   b->order = best_order;
   s = upload_items(b);
   if (s != DG_OK) return s;
   if (b->gexec) {
-    hipGraphExecDestroy(b->gexec);
+    (void)hipGraphExecDestroy(b->gexec);
     b->gexec = nullptr;
   }
   if (best_ms) *best_ms = best;
   return batch_leave(b);
 }
 
-int32_t dg_batch_grid(const dg_batch* b) { return b ? b->grid : 0; }
+int32_t dg_batch_grid(const dg_batch* b) {
+  if (!b) return 0;
+  int total = 0;
+  for (const auto& g : b->groups) total += g.grid;
+  return total;
+}
 
 const char* dg_batch_last_error(const dg_batch* b) {
   if (b) return b->err.c_str();

@@ -63,15 +63,16 @@ hipError_t launch_field(const FieldArgs& a, hipStream_t s);
 hipError_t launch_moments_reduce(const double* mom, int ntiles, double* ring, const int* counter, hipStream_t s);
 hipError_t launch_reset_counter(int* counter, hipStream_t s);
 
-// Batched persistent stage: `runs` (device) holds one StageArgs<float> per
-// run, `kind` (device) 10*n + nv per run, `items` (device) the (run, tile)
-// work list, `xcd_begin` (device, 9 entries) its split over the 8 XCDs.
-hipError_t launch_stage_batched(bool un, const StageArgs<float>* runs, const int* kind, const int2* items,
-                                const int* xcd_begin, int grid, hipStream_t s);
+// Batched persistent stage of one kind (n, nv): `runs` (device) holds one
+// StageArgs<float> per run of the batch, `items` (device) the kind's (run,
+// tile) work list, `xcd_begin` (device, 9 entries, relative to `items`) its
+// split over the 8 XCDs.
+hipError_t launch_stage_batched(bool un, int n, int nv, const StageArgs<float>* runs, const int2* items, const int* xcd_begin,
+                                int grid, hipStream_t s);
 // Batched field solve: `fa` (device) one FieldArgs per run, `xitems` (device)
 // the (run, x element) list.
 hipError_t launch_field_batched(const FieldArgs* fa, const int2* xitems, int nxitems, int nruns, int max_pmax, hipStream_t s);
-// Resident work-groups per CU of the batched stage kernel.
-int batched_occupancy(bool un);
+// Resident work-groups per CU of the batched stage kernel of a kind.
+int batched_occupancy(bool un, int n, int nv);
 
 }  // namespace dgk

@@ -216,15 +216,23 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   const unsigned c0 = iv0 * N;                                  // first v node of the chunk
   // byte offset of (row (jx, iu', ju), chunk start) inside one x element
   auto soff = [&](int jx, int iue, int ju) -> unsigned { return ((jx * NUn + iue * N + ju) * NVn + c0) * S; };
+  // Rows (jx, iu, 0..N-1) are rowb bytes apart: their common part goes in the
+  // lane offset (one VALU add per x node; idle lanes stay out of range) and
+  // ju * rowb in the scalar offset, so only N distinct scalar offsets are live
+  // instead of one per row of the slab.
+  const unsigned rowb = NVn * S;
+  auto vrow = [&](int jx, int iue) -> unsigned { return vo + ((jx * NUn + iue * N) * NVn + c0) * S; };
   const auto rf = xelem_rsrc(a.fin, xstride, ix, xbytes);
   const auto ru = xelem_rsrc(a.fun, xstride, ix, xbytes);
   const auto ro = xelem_rsrc(a.out, xstride, ix, xbytes);
 
   T f[N][N];
 #pragma unroll
-  for (int jx = 0; jx < N; ++jx)
+  for (int jx = 0; jx < N; ++jx) {
+    const unsigned vj = vrow(jx, iu);
 #pragma unroll
-    for (int ju = 0; ju < N; ++ju) f[jx][ju] = B::ld(rf, vo, soff(jx, iu, ju));
+    for (int ju = 0; ju < N; ++ju) f[jx][ju] = B::ld(rf, vj, ju * rowb);
+  }
 
   // x faces: the x speed u is uniform per u node, so the upwind side (left
   // neighbour's last node or right neighbour's first node) is too.
@@ -238,8 +246,8 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
     for (int ju = 0; ju < N; ++ju) {
       const T uu = a.ucoord[iu * N + ju];
       T h;
-      if (uu > T(0)) h = B::ld(rxl, vo, soff(N - 1, iu, ju));
-      else h = B::ld(rxr, vo, soff(0, iu, ju));
+      if (uu > T(0)) h = B::ld(rxl, vrow(N - 1, iu), ju * rowb);
+      else h = B::ld(rxr, vrow(0, iu), ju * rowb);
       xh[ju] = uu == T(0) ? T(0) : h;
     }
   }
@@ -295,7 +303,7 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   T unr[N];
   if (UN) {
 #pragma unroll
-    for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld(ru, vo, soff(0, iu, ju));
+    for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld(ru, vrow(0, iu), ju * rowb);
   }
   T uh = uface(0);
 
@@ -311,26 +319,30 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   };
   // stage combination, store and FP64 density partial of a finished row
   auto finish_row = [&](int jx, const T* acc, const T* lo) {
-    T vrow[N];
+    T vout[N];
 #pragma unroll
     for (int ju = 0; ju < N; ++ju) {
       const T rhs = acc[ju] + lo[ju * ROW + 1 + lane];
-      T v = fmadd(a.c_dt, rhs, a.c_in * f[jx][ju]);
-      if (UN) v = fmadd(a.c_un, unr[ju], v);
-      vrow[ju] = v;
+      // with u^n: f + c_un (u^n - f) = c_un u^n + (1 - c_un) f; a nearly
+      // steady state then stays bit-identical instead of picking up the same
+      // rounding every step (a mass drift in FP32)
+      const T base = UN ? fmadd(a.c_un, unr[ju] - f[jx][ju], f[jx][ju]) : a.c_in * f[jx][ju];
+      vout[ju] = fmadd(a.c_dt, rhs, base);
     }
     // next u^n row issued before this row's stores (loads and stores share one
     // in-order completion counter)
     if (UN && jx + 1 < N) {
+      const unsigned vj = vrow(jx + 1, iu);
 #pragma unroll
-      for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld(ru, vo, soff(jx + 1, iu, ju));
+      for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld(ru, vj, ju * rowb);
     }
     // density partial: (du/2) sum_ju w_ju v, reference weights as literals
     double sum = 0.0;
+    const unsigned vj = vrow(jx, iu);
 #pragma unroll
     for (int ju = 0; ju < N; ++ju) {
-      B::st(vrow[ju], ro, vo, soff(jx, iu, ju));
-      sum = __builtin_fma(K.w[ju], static_cast<double>(vrow[ju]), sum);
+      B::st(vout[ju], ro, vj, ju * rowb);
+      sum = __builtin_fma(K.w[ju], static_cast<double>(vout[ju]), sum);
     }
     if (a.partials) {
       // idle lanes: select, never multiply by a zero weight
@@ -491,8 +503,8 @@ __device__ __forceinline__ void stage1v_tile(const StageArgs<T> a, int bid, T* l
 #pragma unroll
   for (int jx = 0; jx < N; ++jx) {
     const T rhs = acc[jx] + lds[jx * ROW + 1 + lane];
-    T v = fmadd(a.c_dt, rhs, a.c_in * f[jx]);
-    if (UN) v = fmadd(a.c_un, B::ld(ru, vo, soff(jx)), v);
+    const T base = UN ? fmadd(a.c_un, B::ld(ru, vo, soff(jx)) - f[jx], f[jx]) : a.c_in * f[jx];
+    const T v = fmadd(a.c_dt, rhs, base);
     B::st(v, ro, vo, soff(jx));
     if (a.partials) {
       const double s = wave_sum(act ? wvl * static_cast<double>(v) : 0.0);
@@ -794,43 +806,30 @@ __global__ void moments_reduce_kernel(const double* mom, int ntiles, double* rin
 __global__ void reset_counter_kernel(int* c) { *c = 0; }
 
 // -------------------------------------------------------------------------
-// Batched persistent stage kernel: many independent runs (1D1V and 1D2V, any
-// n in 2..9, FP32 storage) in one launch.  The host builds a work list of
-// (run, tile) items ordered by decreasing tile cost and split into 8
-// contiguous ranges, one per XCD; work-group b serves range b % 8 with a
-// stride of the number of work-groups on that XCD, so the waves of one XCD
-// walk neighbouring tiles together.  Each item runs the same tile code as the
-// single-run kernels.
+// Batched persistent stage kernels: many independent runs (1D1V and 1D2V, n
+// in 2..9, FP32 storage).  Runs are grouped by kind (n, velocity dimension);
+// each kind gets one persistent launch per RK stage, specialised like the
+// single-run kernels (a single launch for every kind would carry the largest
+// kind's register allocation and run every kind at its occupancy).  The host
+// builds each kind's (run, tile) work list, ordered by decreasing tile cost
+// and split into 8 contiguous ranges, one per XCD; work-group b serves range
+// b % 8 with a stride of the number of work-groups on that XCD, so the waves
+// of one XCD walk neighbouring tiles together.
 // -------------------------------------------------------------------------
-template <int N>
-constexpr int lds_words_any() { return lds_words_2v<N>() > lds_words_1v<N>() ? lds_words_2v<N>() : lds_words_1v<N>(); }
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int kBatchLds = cmax(cmax(cmax(lds_words_any<2>(), lds_words_any<3>()), cmax(lds_words_any<4>(), lds_words_any<5>())),
-                               cmax(cmax(lds_words_any<6>(), lds_words_any<7>()), cmax(lds_words_any<8>(), lds_words_any<9>())));
-
-template <bool UN>
+template <bool UN, int N, int NV>
 __global__ void __launch_bounds__(kWave, 2) stage_batched_kernel(const StageArgs<float>* __restrict__ runs,
-                                                                  const int* __restrict__ kind,
                                                                   const int2* __restrict__ items,
                                                                   const int* __restrict__ xcd_begin) {
-  __shared__ float lds[kBatchLds];
-  __shared__ float hbuf[kMaxN * kMaxN];
+  __shared__ float lds[NV == 2 ? lds_words_2v<N>() : lds_words_1v<N>()];
+  __shared__ float hbuf[NV == 2 ? N * N : 1];
   const int b = blockIdx.x, c = b & 7, slot = b >> 3, g = gridDim.x;
   const int slots = (g >> 3) + (c < (g & 7) ? 1 : 0);
   const int end = xcd_begin[c + 1];
   for (int i = xcd_begin[c] + slot; i < end; i += slots) {
     const int2 it = items[i];
-    const int r = it.x, t = it.y;
-    const StageArgs<float> a = runs[r];
-    switch (kind[r]) {   // 10 * n + nv
-#define DG_BATCH_CASE(NN)                                                          \
-  case 10 * NN + 2: stage2v_tile<float, NN, UN>(a, t, lds, hbuf); break;           \
-  case 10 * NN + 1: stage1v_tile<float, NN, UN>(a, t, lds); break;
-      DG_BATCH_CASE(2) DG_BATCH_CASE(3) DG_BATCH_CASE(4) DG_BATCH_CASE(5)
-      DG_BATCH_CASE(6) DG_BATCH_CASE(7) DG_BATCH_CASE(8) DG_BATCH_CASE(9)
-#undef DG_BATCH_CASE
-      default: break;
-    }
+    const StageArgs<float> a = runs[it.x];
+    if (NV == 2) stage2v_tile<float, N, UN>(a, it.y, lds, hbuf);
+    else stage1v_tile<float, N, UN>(a, it.y, lds);
     wave_lds_order();
   }
 }
@@ -923,11 +922,46 @@ hipError_t launch_moments_reduce(const double* mom, int ntiles, double* ring, co
   return hipGetLastError();
 }
 
-hipError_t launch_stage_batched(bool un, const StageArgs<float>* runs, const int* kind, const int2* items,
-                                const int* xcd_begin, int grid, hipStream_t s) {
-  if (un) hipLaunchKernelGGL(stage_batched_kernel<true>, dim3(grid), dim3(kWave), 0, s, runs, kind, items, xcd_begin);
-  else hipLaunchKernelGGL(stage_batched_kernel<false>, dim3(grid), dim3(kWave), 0, s, runs, kind, items, xcd_begin);
+template <int N, int NV>
+static hipError_t stage_batched_t(bool un, const StageArgs<float>* runs, const int2* items, const int* xcd_begin, int grid,
+                                  hipStream_t s) {
+  if (un) hipLaunchKernelGGL((stage_batched_kernel<true, N, NV>), dim3(grid), dim3(kWave), 0, s, runs, items, xcd_begin);
+  else hipLaunchKernelGGL((stage_batched_kernel<false, N, NV>), dim3(grid), dim3(kWave), 0, s, runs, items, xcd_begin);
   return hipGetLastError();
+}
+
+template <int N, int NV>
+static int batched_occ_t(bool un) {
+  int nb = 0;
+  hipError_t e = un ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_batched_kernel<true, N, NV>, kWave, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_batched_kernel<false, N, NV>, kWave, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
+hipError_t launch_stage_batched(bool un, int n, int nv, const StageArgs<float>* runs, const int2* items, const int* xcd_begin,
+                                int grid, hipStream_t s) {
+  if (grid < 1) return hipErrorInvalidValue;
+  switch (10 * n + nv) {
+#define DG_BATCH_CASE(NN)                                                         \
+  case 10 * NN + 2: return stage_batched_t<NN, 2>(un, runs, items, xcd_begin, grid, s); \
+  case 10 * NN + 1: return stage_batched_t<NN, 1>(un, runs, items, xcd_begin, grid, s);
+    DG_BATCH_CASE(2) DG_BATCH_CASE(3) DG_BATCH_CASE(4) DG_BATCH_CASE(5)
+    DG_BATCH_CASE(6) DG_BATCH_CASE(7) DG_BATCH_CASE(8) DG_BATCH_CASE(9)
+#undef DG_BATCH_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int batched_occupancy(bool un, int n, int nv) {
+  switch (10 * n + nv) {
+#define DG_BATCH_CASE(NN)                              \
+  case 10 * NN + 2: return batched_occ_t<NN, 2>(un); \
+  case 10 * NN + 1: return batched_occ_t<NN, 1>(un);
+    DG_BATCH_CASE(2) DG_BATCH_CASE(3) DG_BATCH_CASE(4) DG_BATCH_CASE(5)
+    DG_BATCH_CASE(6) DG_BATCH_CASE(7) DG_BATCH_CASE(8) DG_BATCH_CASE(9)
+#undef DG_BATCH_CASE
+    default: return 0;
+  }
 }
 
 hipError_t launch_field_batched(const FieldArgs* fa, const int2* xitems, int nxitems, int nruns, int max_pmax, hipStream_t s) {
@@ -938,12 +972,6 @@ hipError_t launch_field_batched(const FieldArgs* fa, const int2* xitems, int nxi
   return hipGetLastError();
 }
 
-int batched_occupancy(bool un) {
-  int nb = 0;
-  hipError_t e = un ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_batched_kernel<true>, kWave, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_batched_kernel<false>, kWave, 0);
-  return e == hipSuccess ? nb : 0;
-}
 
 hipError_t launch_reset_counter(int* counter, hipStream_t s) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);

@@ -311,7 +311,7 @@ dg_status dg_nn_init(const int32_t* sizes, int32_t nlayers, int32_t max_rows, vo
   e = hipMemsetAsync(nn->ws + L.off_P, 0, L.off_Ytmp - L.off_P, nn->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(nn->stream);
   if (e != hipSuccess) {
-    hipEventDestroy(nn->ev);
+    (void)hipEventDestroy(nn->ev);
     delete nn;
     return init_fail(DG_ERR_DEVICE, std::string("workspace clear: ") + hipGetErrorString(e));
   }
@@ -322,7 +322,7 @@ dg_status dg_nn_init(const int32_t* sizes, int32_t nlayers, int32_t max_rows, vo
 dg_status dg_nn_destroy(dg_nn* nn) {
   if (!nn) return DG_OK;
   hipError_t e = hipStreamSynchronize(nn->stream);
-  hipEventDestroy(nn->ev);
+  (void)hipEventDestroy(nn->ev);
   delete nn;
   return e == hipSuccess ? DG_OK : DG_ERR_DEVICE;
 }

@@ -227,59 +227,79 @@ class LearnedCorrection:
                                     dt, nsteps, diag=True)
         return self.coarse.step(fc, dt, nsteps, diag=True)
 
-    def evaluate(self, seed, coarse_steps, log=None):
-        """Field-energy histories of the fine run, the plain coarse run and the
-        corrected coarse run from the same initial state, compared at the
-        coarse step times (fine history interpolated linearly in time)."""
+    def evaluate(self, seed, coarse_steps, checkpoints=10, log=None):
+        """Fine run, plain coarse run and corrected coarse run from the same
+        initial state (the coarse ones from its projection).  The fine step is
+        the coarse step divided by an integer m, so both grids meet at every
+        coarse step time.  Compared: field-energy histories at the coarse
+        times, and at `checkpoints` evenly spaced times the relative L2
+        distance of each coarse state from the projected fine state."""
+        t = self.torch
         f = self.initial_fine_state(seed)
         fc0 = self.project(f)
         dtc = self.coarse_dt(fc0)
-        dtf = self.fine_dt(f)
-        tend = coarse_steps * dtc
-        nf = int(math.ceil(tend / dtf))
-        dtf = tend / nf
+        m = int(math.ceil(dtc / self.fine_dt(f)))
+        dtf = dtc / m
         f0_energy = self.fine.diagnostics(f)["field_energy"]
-        t0 = time.perf_counter()
-        fine = self.fine.step(f, dtf, nf, diag=True)
-        t_fine = time.perf_counter() - t0
-        tf = np.concatenate([[0.0], np.arange(1, nf + 1) * dtf])
-        wf = np.concatenate([[f0_energy], [d["field_energy"] for d in fine]])
-        a = fc0.clone()
-        b = fc0.clone()
-        t0 = time.perf_counter()
-        plain = self.run_coarse(a, dtc, coarse_steps, False)
-        t_plain = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        corr = self.run_coarse(b, dtc, coarse_steps, True)
-        t_corr = time.perf_counter() - t0
-        tc = np.arange(1, coarse_steps + 1) * dtc
-        ref = np.interp(tc, tf, wf)
-        wp = np.array([d["field_energy"] for d in plain])
-        wc = np.array([d["field_energy"] for d in corr])
+        m0 = self.coarse.diagnostics(fc0)["mass"]
+        plain_s, nn_s = fc0.clone(), fc0.clone()
+        ck = sorted(set(int(round(coarse_steps * (i + 1) / checkpoints)) for i in range(checkpoints)))
+        wf, wp, wc = [], [], []
+        err_p, err_c, times = [], [], []
+        tim = {"fine": 0.0, "plain_coarse": 0.0, "coarse_nn": 0.0}
+        done = 0
+        pf = self.coarse.empty_state()
+        for k in ck:
+            nstep = k - done
+            t0 = time.perf_counter()
+            fine = self.fine.step(f, dtf, nstep * m, diag=True)
+            t.cuda.synchronize()
+            t1 = time.perf_counter()
+            plain = self.run_coarse(plain_s, dtc, nstep, False)
+            t.cuda.synchronize()
+            t2 = time.perf_counter()
+            corr = self.run_coarse(nn_s, dtc, nstep, True)
+            t.cuda.synchronize()
+            t3 = time.perf_counter()
+            tim["fine"] += t1 - t0
+            tim["plain_coarse"] += t2 - t1
+            tim["coarse_nn"] += t3 - t2
+            wf += [d["field_energy"] for d in fine[m - 1::m]]
+            wp += [d["field_energy"] for d in plain]
+            wc += [d["field_energy"] for d in corr]
+            self.project(f, pf)
+            nrm = float(t.linalg.vector_norm(pf.double()))
+            err_p.append(float(t.linalg.vector_norm((plain_s - pf).double())) / nrm)
+            err_c.append(float(t.linalg.vector_norm((nn_s - pf).double())) / nrm)
+            times.append(k * dtc)
+            done = k
+        ref, wp, wc = np.array(wf), np.array(wp), np.array(wc)
 
         def rel(w):
             return float(np.linalg.norm(w - ref) / np.linalg.norm(ref))
 
         def relmax(w):
-            return float(np.max(np.abs(w - ref) / np.abs(ref)))
+            return float(np.max(np.abs(w - ref)) / np.max(np.abs(ref)))
 
         out = {
-            "seed": seed, "coarse_steps": coarse_steps, "dt_coarse": dtc, "fine_steps": nf, "dt_fine": dtf,
-            "t_end": tend,
+            "seed": seed, "coarse_steps": coarse_steps, "dt_coarse": dtc, "fine_steps": coarse_steps * m,
+            "dt_fine": dtf, "t_end": coarse_steps * dtc, "field_energy_t0": f0_energy,
             "field_energy_rel_l2": {"plain_coarse": rel(wp), "coarse_nn": rel(wc)},
-            "field_energy_rel_max": {"plain_coarse": relmax(wp), "coarse_nn": relmax(wc)},
-            "mass_drift": {"plain_coarse": abs(plain[-1]["mass"] - plain[0]["mass"]) / plain[0]["mass"],
-                           "coarse_nn": abs(corr[-1]["mass"] - corr[0]["mass"]) / corr[0]["mass"]},
-            "wall_s": {"fine": t_fine, "plain_coarse": t_plain, "coarse_nn": t_corr},
+            "field_energy_max_err_over_max": {"plain_coarse": relmax(wp), "coarse_nn": relmax(wc)},
+            "state_rel_l2_vs_projected_fine": {"t": times, "plain_coarse": err_p, "coarse_nn": err_c},
+            "mass_drift": {"plain_coarse": abs(plain[-1]["mass"] - m0) / m0, "coarse_nn": abs(corr[-1]["mass"] - m0) / m0},
+            "wall_s": tim,
             "dof_updates_per_sim_time": {
                 "fine": self.fine_dof() * 3 / dtf,
                 "coarse": self.coarse_dof() * 3 / dtc,
             },
-            "history": {"t": tc.tolist(), "fine": ref.tolist(), "plain": wp.tolist(), "nn": wc.tolist()},
+            "history": {"t": (np.arange(1, len(ref) + 1) * dtc).tolist(), "fine": ref.tolist(), "plain": wp.tolist(),
+                        "nn": wc.tolist()},
         }
         if log:
-            log("eval seed %d: rel L2 plain %.4f nn %.4f" % (seed, out["field_energy_rel_l2"]["plain_coarse"],
-                                                            out["field_energy_rel_l2"]["coarse_nn"]))
+            log("eval seed %d: field energy rel L2 plain %.4f nn %.4f; state error at end plain %.3e nn %.3e"
+                % (seed, out["field_energy_rel_l2"]["plain_coarse"], out["field_energy_rel_l2"]["coarse_nn"],
+                   err_p[-1], err_c[-1]))
         return out
 
     def fine_dof(self):

@@ -209,3 +209,27 @@ def test_rhs_is_deterministic_and_graph_replays_match_eager():
     r1 = s.rhs(a)
     r2 = s.rhs(a)
     assert torch.equal(r1, r2)
+
+
+@pytest.mark.parametrize("nv", [1, 2])
+def test_fp32_long_run_conserves_mass(nv):
+    """FP32 storage over 600 steps: the stage coefficients sum to exactly one
+    in FP32, so the mass moves only by unbiased rounding (random walk of
+    ~1e-10 per stage), far inside 1e-6."""
+    print("fp32 long-run mass", nv, flush=True)
+    if nv == 2:
+        nelem, lo, hi, wc = [16, 16, 16], [0.0, -8.0, -8.0], [4 * math.pi, 8.0, 8.0], 1.0
+        s, g = _setup(2, 4, nelem, lo, hi, wc)
+        c = g.coords()
+        f0 = inputs.mixture(c[0], c[1], c[2], 0.6, 1.0, 0.5, 1e-3, 3.0)
+    else:
+        nelem, lo, hi = [16, 32], [0.0, -8.0], [4 * math.pi, 8.0]
+        s, g = _setup(1, 4, nelem, lo, hi)
+        c = g.coords()
+        f0 = inputs.landau(c[0], c[1], 0.5, 0.01)
+    fd = _dev(f0, s)
+    m0 = s.diagnostics(fd)["mass"]
+    dt = 0.9 * s.dt_max(float(s.poisson(fd).abs().max()))
+    recs = s.step(fd, dt, 600, diag=True)
+    drift = max(abs(r["mass"] - m0) for r in recs) / m0
+    assert drift < 1e-6, drift

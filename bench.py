@@ -220,7 +220,9 @@ def main():
     bytes_per_launch = [2 * esize * dof, 3 * esize * dof, 3 * esize * dof]
     tot_bytes = sum(bytes_per_launch) * prof.shape[0]
     achieved = tot_bytes / (st_ms.sum() / 1e3) / 1e9
-    traffic = load_traffic(wl.name + "_" + wl.storage)
+    traffic_stages = load_traffic(wl.name + "_" + wl.storage)
+    # per launch, averaged over the three stage launches like `achieved`
+    traffic = sum(traffic_stages) / len(traffic_stages) if traffic_stages else None
     if args.copy_calibration:
         buf = torch.empty_like(f)
         for _ in range(2):
@@ -246,6 +248,8 @@ def main():
                    "reductions": "f64", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_per_stage_launch": traffic_stages,
+                     "algorithmic_bytes_mean_per_launch": sum(bytes_per_launch) / 3.0,
                      "kernel": "stage%dv_kernel<%s,%d>" % (wl.nv, "float" if esize == 4 else "double", wl.n),
                      "stage_ms_mean": [float(x) for x in st_ms.mean(axis=0)],
                      "field_ms_mean": [float(x) for x in fld_ms.mean(axis=0)],

@@ -169,6 +169,15 @@ struct dg_nn {
   int64_t t = 0;   // AdamW step count
   bool have_grads = false;
   std::string err = "no error";
+  // cached graph of one corrected coarse step and what it was captured for
+  hipGraphExec_t gexec = nullptr;
+  const void* g_ctx = nullptr;
+  const void* g_f = nullptr;
+  const void* g_mean = nullptr;
+  const void* g_inv = nullptr;
+  double g_dt = 0.0;
+  float g_scale = 0.0f;
+  bool g_diag = false;
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
 
@@ -322,6 +331,7 @@ dg_status dg_nn_init(const int32_t* sizes, int32_t nlayers, int32_t max_rows, vo
 dg_status dg_nn_destroy(dg_nn* nn) {
   if (!nn) return DG_OK;
   hipError_t e = hipStreamSynchronize(nn->stream);
+  if (nn->gexec) (void)hipGraphExecDestroy(nn->gexec);
   (void)hipEventDestroy(nn->ev);
   delete nn;
   return e == hipSuccess ? DG_OK : DG_ERR_DEVICE;
@@ -625,6 +635,56 @@ dg_status corrected_stage(dg_ctx* c, dg_nn* nn, const float* mean, const float* 
   return dgi::field(c, E, nullptr, record);
 }
 
+// One corrected SSP-RK3 step (three corrected stages; moments when diag).
+dg_status corrected_step(dg_ctx* c, dg_nn* nn, const float* mean, const float* inv_std, float scale, void* f,
+                         double dt, bool diag) {
+  void* B = c->ws + c->L.off_B;
+  void* C = c->ws + c->L.off_C;
+  NN_TRY(corrected_stage(c, nn, mean, inv_std, scale, f, nullptr, B, 0.0, 1.0, dt, false));
+  NN_TRY(corrected_stage(c, nn, mean, inv_std, scale, B, f, C, 0.75, 0.25, 0.25 * dt, false));
+  NN_TRY(corrected_stage(c, nn, mean, inv_std, scale, C, f, f, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt, diag));
+  if (diag) NN_TRY(dgi::moments(c, f));
+  return DG_OK;
+}
+
+// The corrected step is ~45 short launches; it is captured once per
+// (context, state, dt, statistics, scale, diag) and replayed.  Parameter
+// updates need no new capture: the network's buffers keep their addresses.
+dg_status build_corrected_graph(dg_ctx* c, dg_nn* nn, const float* mean, const float* inv_std, float scale, void* f,
+                                double dt, bool diag) {
+  if (nn->gexec && nn->g_ctx == c && nn->g_f == f && nn->g_mean == mean && nn->g_inv == inv_std && nn->g_dt == dt &&
+      nn->g_scale == scale && nn->g_diag == diag)
+    return DG_OK;
+  if (nn->gexec) {
+    (void)hipGraphExecDestroy(nn->gexec);
+    nn->gexec = nullptr;
+  }
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return dgi::hip_fail(c, e, "hipStreamBeginCapture");
+  dg_status s = corrected_step(c, nn, mean, inv_std, scale, f, dt, diag);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->stream, &g);
+  if (s != DG_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return dgi::hip_fail(c, e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&nn->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    nn->gexec = nullptr;
+    return dgi::hip_fail(c, e, "hipGraphInstantiate");
+  }
+  nn->g_ctx = c;
+  nn->g_f = f;
+  nn->g_mean = mean;
+  nn->g_inv = inv_std;
+  nn->g_dt = dt;
+  nn->g_scale = scale;
+  nn->g_diag = diag;
+  return DG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -642,21 +702,16 @@ dg_status dg_nn_rk_step(dg_ctx* coarse, dg_nn* nn, const float* mean, const floa
   if (e != hipSuccess) return dgi::hip_fail(coarse, e, "network stream ordering");
   NN_TRY(dgi::begin_steps(coarse, f, dt, nsteps));
   const dgi::Layout& L = coarse->L;
-  void* B = coarse->ws + L.off_B;
-  void* C = coarse->ws + L.off_C;
   const bool diag = host_diag != nullptr;
+  NN_TRY(build_corrected_graph(coarse, nn, mean, inv_std, out_scale, f, dt, diag));
   bool bad = false;
   int done = 0;
   while (done < nsteps) {
     const int chunk = std::min(nsteps - done, dgk::kRing);
     if (diag && (e = dgk::launch_reset_counter(coarse->at<int>(L.off_ctr), coarse->stream)) != hipSuccess)
       return dgi::hip_fail(coarse, e, "counter reset");
-    for (int k = 0; k < chunk; ++k) {
-      NN_TRY(corrected_stage(coarse, nn, mean, inv_std, out_scale, f, nullptr, B, 0.0, 1.0, dt, false));
-      NN_TRY(corrected_stage(coarse, nn, mean, inv_std, out_scale, B, f, C, 0.75, 0.25, 0.25 * dt, false));
-      NN_TRY(corrected_stage(coarse, nn, mean, inv_std, out_scale, C, f, f, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt, diag));
-      if (diag) NN_TRY(dgi::moments(coarse, f));
-    }
+    for (int k = 0; k < chunk; ++k)
+      if ((e = hipGraphLaunch(nn->gexec, coarse->stream)) != hipSuccess) return dgi::hip_fail(coarse, e, "hipGraphLaunch");
     if (diag) {
       std::vector<double> ring(static_cast<size_t>(chunk) * 8);
       e = hipMemcpyAsync(ring.data(), coarse->at<double>(L.off_ring), ring.size() * 8, hipMemcpyDeviceToHost, coarse->stream);

@@ -129,15 +129,15 @@ __global__ void scatter_kernel(ScatterArgs a) {
   const int iu = static_cast<int>((e / a.Nv) % a.Nu);
   const int ix = static_cast<int>(e / (static_cast<size_t>(a.Nv) * a.Nu));
   const float* y = a.Y + e * a.ldy;
-  float num = 0.0f, den = 0.0f;
+  double num = 0.0, den = 0.0;   // FP64: the removed mean must not carry a rounding bias
   for (int jx = 0; jx < n; ++jx)
     for (int ju = 0; ju < n; ++ju)
       for (int jv = 0; jv < n; ++jv) {
-        const float w = a.w[jx] * a.w[ju] * a.w[jv];
+        const double w = static_cast<double>(a.w[jx]) * a.w[ju] * a.w[jv];
         num += w * y[(jx * n + ju) * n + jv];
         den += w;
       }
-  const float mean = a.mass_neutral ? num / den : 0.0f;
+  const float mean = a.mass_neutral ? static_cast<float>(num / den) : 0.0f;
   for (int jx = 0; jx < n; ++jx)
     for (int ju = 0; ju < n; ++ju)
       for (int jv = 0; jv < n; ++jv) {

@@ -39,9 +39,9 @@ class Config:
     hidden: List[int] = field(default_factory=lambda: [128, 128, 128])
     train_seeds: List[int] = field(default_factory=lambda: list(range(32)))
     snapshots_per_run: int = 64
-    snapshot_stride: int = 16          # fine steps between snapshots
+    snapshot_stride: int = 220         # fine steps between snapshots (64 x 220 spans t = 0..9)
     spinup_steps: int = 0              # fine steps before the first snapshot
-    epochs: int = 3
+    epochs: int = 5
     lr: float = 1e-3
     weight_decay: float = 1e-4
     init_seed: int = 12345
@@ -319,8 +319,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="train and evaluate the learned coarse-grid correction")
     ap.add_argument("--runs", type=int, default=32)
     ap.add_argument("--snapshots", type=int, default=64)
-    ap.add_argument("--stride", type=int, default=16)
-    ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--stride", type=int, default=220)
+    ap.add_argument("--epochs", type=int, default=5)
     ap.add_argument("--eval-seeds", type=int, nargs="*", default=[1000, 1001])
     ap.add_argument("--coarse-steps", type=int, default=2000)
     ap.add_argument("--out", default=None)
@@ -344,7 +344,7 @@ def main(argv=None):
     t_train = time.perf_counter() - t0
     err1 = lc.relative_error(X[-nval:], T[-nval:])
     # held-out runs: one-step closure error and field-energy histories
-    hs, hf, ht = lc.generate(a.eval_seeds, nsnap=8)
+    hs, hf, ht = lc.generate(a.eval_seeds, nsnap=16, stride=4 * a.stride)
     Xh, Th = lc.dataset(hs, hf, ht)
     err_h = lc.relative_error(Xh, Th)
     evals = [lc.evaluate(s, a.coarse_steps, log=log) for s in a.eval_seeds]

@@ -334,3 +334,32 @@ def test_corrected_step_matches_oracle(scale):
         wts = g.weights()
         assert abs(np.sum(wts * got) - np.sum(wts * fh)) < 1e-5 * np.sum(wts * fh)
     net.close()
+
+
+def test_corrected_step_graph_replays_match_separate_calls():
+    """The corrected step is replayed from a captured graph: three replays in
+    one call must equal three one-step calls (each with its own eager field
+    solve in between) bit for bit."""
+    n, nelem = 4, [4, 3, 5]
+    lo, hi = [0.0, -6.0, -6.0], [4 * math.pi, 6.0, 6.0]
+    s = dg.Solver(2, n, nelem, lo, hi, 1.0)
+    g = grid.PhaseGrid(2, n, nelem, lo, hi, 1.0)
+    c = g.coords()
+    f0 = torch.from_numpy(inputs.mixture(c[0], c[1], c[2], 0.5, 1.0, 0.5, 0.05, 3.0)).float().cuda()
+    ne, nfeat = 60, 7 * n ** 3 + n
+    sizes = [nfeat, 32, 32, n ** 3]
+    net = dg.Network(sizes, ne)
+    ps = _he_params(sizes, 4)
+    ps[-2] = ps[-2] * 0.01
+    net.set_params(dg.Network.flatten(ps))
+    mean = torch.zeros(nfeat, device="cuda")
+    inv = torch.full((nfeat,), 2.0, device="cuda")
+    dt = 0.5 * s.dt_max(float(s.poisson(f0).abs().max()))
+    a, b = f0.clone(), f0.clone()
+    recs = dg.dg_nn_rk_step(s.ctx, net.nn, mean, inv, 0.5, a, dt, 3, diag=True)
+    for _ in range(3):
+        dg.dg_nn_rk_step(s.ctx, net.nn, mean, inv, 0.5, b, dt, 1)
+        torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert len(recs) == 3 and all(r["finite"] for r in recs)
+    net.close()

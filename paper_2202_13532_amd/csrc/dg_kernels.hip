@@ -619,7 +619,7 @@ __global__ void __launch_bounds__(kWave) moments_kernel(StageArgs<T> a, double* 
 //           z_p = z_{p-1} z_1, and writes the diagnostics record.
 // No float atomics: results are bitwise reproducible.
 // -------------------------------------------------------------------------
-constexpr int kFieldB = 256;
+constexpr int kFieldB = 1024;
 
 constexpr int kFieldA = 256;
 
@@ -627,6 +627,19 @@ __device__ __forceinline__ void fieldA_body(const FieldArgs& a, int ix) {
   __shared__ double dens[kMaxN];
   __shared__ double red[kFieldA / kWave][kMaxN];
   const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave, n = a.n;
+  // the connection-tensor entries of this thread's first mode do not depend
+  // on the density: fetch them together with the partials (one memory round
+  // trip instead of two)
+  double tr[kMaxN], ti[kMaxN];
+  if (tid < a.pmax) {
+#pragma unroll
+    for (int j = 0; j < kMaxN; ++j)
+      if (j < n) {
+        const double* t = a.T + 2 * (static_cast<size_t>(ix * n + j) * a.pmax + tid);
+        tr[j] = t[0];
+        ti[j] = t[1];
+      }
+  }
   // thread-strided partial sums for all x nodes at once (n loads in flight),
   // wave sums, then the waves' results added in order
   double s[kMaxN];
@@ -655,11 +668,21 @@ __device__ __forceinline__ void fieldA_body(const FieldArgs& a, int ix) {
   __syncthreads();
   for (int p = tid; p < a.pmax; p += kFieldA) {
     double cr = 0.0, ci = 0.0;
-    for (int j = 0; j < n; ++j) {
-      const double* t = a.T + 2 * (static_cast<size_t>(ix * n + j) * a.pmax + p);
-      const double sj = dens[j] - 1.0;
-      cr = __builtin_fma(t[0], sj, cr);
-      ci = __builtin_fma(t[1], sj, ci);
+    if (p == tid) {
+#pragma unroll
+      for (int j = 0; j < kMaxN; ++j)
+        if (j < n) {
+          const double sj = dens[j] - 1.0;
+          cr = __builtin_fma(tr[j], sj, cr);
+          ci = __builtin_fma(ti[j], sj, ci);
+        }
+    } else {
+      for (int j = 0; j < n; ++j) {
+        const double* t = a.T + 2 * (static_cast<size_t>(ix * n + j) * a.pmax + p);
+        const double sj = dens[j] - 1.0;
+        cr = __builtin_fma(t[0], sj, cr);
+        ci = __builtin_fma(t[1], sj, ci);
+      }
     }
     a.cpart[2 * (static_cast<size_t>(ix) * a.pmax + p) + 0] = cr;
     a.cpart[2 * (static_cast<size_t>(ix) * a.pmax + p) + 1] = ci;
@@ -672,12 +695,12 @@ __device__ __forceinline__ void fieldA_body(const FieldArgs& a, int ix) {
 }
 
 __device__ __forceinline__ void fieldB_body(const FieldArgs& a) {
-  extern __shared__ double csh[];          // 2 * pmax coefficients
+  extern __shared__ double csh[];          // 2 * pmax scaled coefficients
   __shared__ double red[2][kFieldB];
   const int tid = threadIdx.x;
-  // c_p = sum over elements of the element partials: kFieldB/4 groups... each
-  // thread sums a quarter of the elements for one p (8 loads in flight), the
-  // quarters are then added in order.
+  // c_p = sum over elements of the element partials: G groups of threads,
+  // each summing a contiguous G-th of the elements for one p (loads in
+  // flight), the groups' sums then added in order.
   constexpr int G = 4;
   for (int base = 0; base < a.pmax; base += kFieldB / G) {
     const int p = base + tid % (kFieldB / G);
@@ -700,12 +723,14 @@ __device__ __forceinline__ void fieldB_body(const FieldArgs& a) {
         r += red[0][q * (kFieldB / G) + tid];
         i += red[1][q * (kFieldB / G) + tid];
       }
-      csh[2 * (base + tid)] = r;
-      csh[2 * (base + tid) + 1] = i;
       if (a.coeffs) {
         a.coeffs[2 * (base + tid)] = r;
         a.coeffs[2 * (base + tid) + 1] = i;
       }
+      // 2 Re((i / k_p) c_p z) = -(2 / k_p) Im(c_p z): fold -2 / k_p in once
+      const double sc = -2.0 / ((base + tid + 1) * a.k1);
+      csh[2 * (base + tid)] = sc * r;
+      csh[2 * (base + tid) + 1] = sc * i;
     }
     __syncthreads();
   }
@@ -720,15 +745,14 @@ __device__ __forceinline__ void fieldB_body(const FieldArgs& a) {
   }
   const double mass = red[0][0];
   __syncthreads();
+  // E at every x node: the modes by the recurrence z_p = z_{p-1} z_1
   const int nodes = a.Nx * a.n;
   double fe = 0.0, mx = 0.0;
   for (int node = tid; node < nodes; node += kFieldB) {
     const double z1r = a.z1[2 * node], z1i = a.z1[2 * node + 1];
     double zr = z1r, zi = z1i, e = 0.0;
     for (int p = 0; p < a.pmax; ++p) {
-      // 2 Re((i / k) c z) = -(2 / k) Im(c z),  k = (p + 1) k_1
-      const double cr = csh[2 * p], ci = csh[2 * p + 1];
-      e = __builtin_fma(-2.0 / ((p + 1) * a.k1), __builtin_fma(cr, zi, ci * zr), e);
+      e += __builtin_fma(csh[2 * p], zi, csh[2 * p + 1] * zr);
       const double t = zr * z1r - zi * z1i;
       zi = __builtin_fma(zr, z1i, zi * z1r);
       zr = t;

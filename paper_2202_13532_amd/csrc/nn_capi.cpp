@@ -34,7 +34,8 @@ struct NNLayout {
   std::vector<size_t> offW, offb;     // element offsets into the parameter vector
   size_t nparam = 0;
   size_t off_P, off_Pbf, off_G, off_m, off_v, off_Ytmp, off_dA, off_dZ, off_dZb, off_loss, off_sum, off_sumsq,
-      off_Xf, off_Yo, off_corr, total;
+      off_Xf, off_Yo, off_corr, off_gpart, total;
+  size_t gpart_floats = 0;   // split-K scratch of the GEMMs
   std::vector<size_t> off_A, off_Z;   // A[l]: BF16 input of layer l (l >= 1); Z[l]: pre-activation of layer l
 };
 
@@ -86,6 +87,10 @@ NNLayout nn_layout(const int32_t* sizes, int32_t nlayers, int32_t max_rows) {
   N.off_Xf = take(R * N.ld[0] * 2);
   N.off_Yo = take(R * sizes[nlayers] * 4);
   N.off_corr = take(R * sizes[nlayers] * 4);
+  size_t wmm = 0;
+  for (int l = 0; l < nlayers; ++l) wmm = std::max(wmm, static_cast<size_t>(sizes[l]) * sizes[l + 1]);
+  N.gpart_floats = std::max(4 * R * static_cast<size_t>(N.wmax), 32 * wmm);
+  N.off_gpart = take(N.gpart_floats * 4);
   N.total = o;
   return N;
 }
@@ -166,6 +171,7 @@ struct dg_nn {
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;
+  int cus = 256;   // compute units of the device (split-K sizing)
   int64_t t = 0;   // AdamW step count
   bool have_grads = false;
   std::string err = "no error";
@@ -219,6 +225,10 @@ dgn::GemmArgs gemm(const uint16_t* A, size_t sam, size_t sak, const uint16_t* B,
   return g;
 }
 
+hipError_t run_gemm(dg_nn* nn, const dgn::GemmArgs& g, hipStream_t s) {
+  return dgn::launch_gemm_tiled(g, nn->at<float>(nn->N.off_gpart), nn->N.gpart_floats, nn->cus, s);
+}
+
 // Forward pass on `s`: X (rows x ld[0] BF16) -> Y (rows x sizes[L] FP32).  With
 // `keep`, the pre-activations are stored for the backward pass.
 dg_status forward_on(dg_nn* nn, const uint16_t* X, int rows, float* Y, bool keep, hipStream_t s) {
@@ -228,7 +238,7 @@ dg_status forward_on(dg_nn* nn, const uint16_t* X, int rows, float* Y, bool keep
     const int in = N.sizes[l], out = N.sizes[l + 1];
     const bool last = l == N.L - 1;
     float* Yt = nn->at<float>(N.off_Ytmp);
-    NN_HIP(nn, dgn::launch_gemm(gemm(A, N.ld[l], 1, nn->at<uint16_t>(N.off_Pbf) + N.offW[l], out, 1, Yt, out, rows, out, in), s));
+    NN_HIP(nn, run_gemm(nn, gemm(A, N.ld[l], 1, nn->at<uint16_t>(N.off_Pbf) + N.offW[l], out, 1, Yt, out, rows, out, in), s));
     dgn::BiasActArgs b{};
     b.Y = Yt;
     b.bias = nn->at<float>(N.off_P) + N.offb[l];
@@ -310,6 +320,11 @@ dg_status dg_nn_init(const int32_t* sizes, int32_t nlayers, int32_t max_rows, vo
   nn->N = std::move(N);
   nn->ws = static_cast<char*>(workspace);
   nn->stream = static_cast<hipStream_t>(hip_stream);
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) nn->cus = prop.multiProcessorCount;
+  }
   hipError_t e = hipEventCreateWithFlags(&nn->ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     delete nn;
@@ -401,11 +416,11 @@ dg_status dg_nn_loss_grad(dg_nn* nn, const uint16_t* X, const float* T, int32_t 
     const uint16_t* A = l == 0 ? X : nn->at<uint16_t>(N.off_A[l]);
     NN_HIP(nn, dgn::launch_colsum(dZ, rows, out, G + N.offb[l], s));
     // dW = A^T dZ  (in x out, K = rows)
-    NN_HIP(nn, dgn::launch_gemm(gemm(A, 1, N.ld[l], dZb, N.ld[l + 1], 1, G + N.offW[l], out, in, out, rows), s));
+    NN_HIP(nn, run_gemm(nn, gemm(A, 1, N.ld[l], dZb, N.ld[l + 1], 1, G + N.offW[l], out, in, out, rows), s));
     if (l > 0) {
       // dA = dZ W^T  (rows x in, K = out), then through the GELU of layer l-1
       float* dA = nn->at<float>(N.off_dA);
-      NN_HIP(nn, dgn::launch_gemm(gemm(dZb, N.ld[l + 1], 1, Wbf + N.offW[l], 1, out, dA, in, rows, in, out), s));
+      NN_HIP(nn, run_gemm(nn, gemm(dZb, N.ld[l + 1], 1, Wbf + N.offW[l], 1, out, dA, in, rows, in, out), s));
       NN_HIP(nn, dgn::launch_gelu_back(dA, nn->at<float>(N.off_Z[l - 1]), dZ, dZb, rows, in, N.ld[l], s));
     }
   }

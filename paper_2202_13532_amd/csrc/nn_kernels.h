@@ -67,6 +67,10 @@ hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 hipError_t launch_gather_raw(const GatherArgs& a, float* out, hipStream_t s);
 hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
+// LDS-tiled MFMA GEMM with split-K (falls back to launch_gemm when an operand
+// has no unit stride or is not 16-byte aligned).  `part`: device scratch of
+// part_floats floats for the split-K slices; `cus`: compute units.
+hipError_t launch_gemm_tiled(const GemmArgs& g, float* part, size_t part_floats, int cus, hipStream_t s);
 hipError_t launch_bias_act(const BiasActArgs& a, hipStream_t s);
 hipError_t launch_gelu_back(const float* dA, const float* Z, float* dZ, uint16_t* dZb, int rows, int cols, int ld, hipStream_t s);
 hipError_t launch_mse(const float* Y, const float* T, int rows, int cols, int ld, float inv_count, float* dY, uint16_t* dYb,

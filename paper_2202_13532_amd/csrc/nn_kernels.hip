@@ -188,6 +188,121 @@ __global__ void __launch_bounds__(kWave) gemm_bf16_kernel(GemmArgs g) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// LDS-tiled BF16 MFMA GEMM for the network's shapes (rows = 4096 per coarse
+// state; inner and outer sizes 64..464).  A 256-thread work-group computes a
+// 64 x 64 tile of C, each wave a 32 x 32 quarter as 2 x 2 MFMA 16x16 tiles;
+// K advances 32 at a time through LDS, where both operands are stored with
+// k contiguous so that each lane fetches its 4 k values with one 8-byte LDS
+// read.  Global loads are 16 bytes (8 BF16) along the operand's contiguous
+// direction: A with k (AK) or m contiguous, B with n (BN) or k contiguous.
+// Split-K: work-group z covers k in [z Ks, (z+1) Ks); with more than one
+// slice, partial tiles go to `part` (slice-major, M x N each) and
+// gemm_reduce_kernel adds the slices in order (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int kTM = 64, kTN = 64, kTK = 32, kTLd = kTK + 8;   // LDS row: 40 BF16
+
+__device__ __forceinline__ void load8(const uint16_t* base, size_t stride, int start, int bound, uint16_t* out) {
+  // 8 consecutive elements base[(start + i) * stride], zero beyond `bound`
+  if (stride == 1 && start + 8 <= bound) {
+    const uint4 v = *reinterpret_cast<const uint4*>(base + start);
+    out[0] = v.x & 0xffff; out[1] = v.x >> 16; out[2] = v.y & 0xffff; out[3] = v.y >> 16;
+    out[4] = v.z & 0xffff; out[5] = v.z >> 16; out[6] = v.w & 0xffff; out[7] = v.w >> 16;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) out[i] = start + i < bound ? base[static_cast<size_t>(start + i) * stride] : uint16_t(0);
+  }
+}
+
+template <bool AK, bool BN>
+__global__ void __launch_bounds__(256) gemm_bf16_tiled_kernel(GemmArgs g, float* part, int ks) {
+  __shared__ uint16_t As[kTM * kTLd];
+  __shared__ uint16_t Bs[kTN * kTLd];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * kTM, n0 = blockIdx.y * kTN;
+  const int kb = blockIdx.z * ks, ke = min(g.K, kb + ks);
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = kb; k0 < ke; k0 += kTK) {
+    uint16_t v[8];
+    if (AK) {   // thread: row r, k chunk c (8 values along k)
+      const int r = tid >> 2, c = (tid & 3) * 8, m = m0 + r;
+      if (m < g.M) load8(g.A + static_cast<size_t>(m) * g.sam, 1, k0 + c, ke, v);
+      else for (int i = 0; i < 8; ++i) v[i] = 0;
+      *reinterpret_cast<uint4*>(&As[r * kTLd + c]) =
+          uint4{v[0] | (uint32_t(v[1]) << 16), v[2] | (uint32_t(v[3]) << 16), v[4] | (uint32_t(v[5]) << 16),
+                v[6] | (uint32_t(v[7]) << 16)};
+    } else {    // thread: k row kk, m chunk c (8 values along m)
+      const int kk = tid >> 3, c = (tid & 7) * 8, k = k0 + kk;
+      if (k < ke) load8(g.A + static_cast<size_t>(k) * g.sak, 1, m0 + c, g.M, v);
+      else for (int i = 0; i < 8; ++i) v[i] = 0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) As[(c + i) * kTLd + kk] = v[i];
+    }
+    if (BN) {   // thread: k row kk, n chunk c
+      const int kk = tid >> 3, c = (tid & 7) * 8, k = k0 + kk;
+      if (k < ke) load8(g.B + static_cast<size_t>(k) * g.sbk, 1, n0 + c, g.N, v);
+      else for (int i = 0; i < 8; ++i) v[i] = 0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Bs[(c + i) * kTLd + kk] = v[i];
+    } else {    // thread: column r, k chunk c
+      const int r = tid >> 2, c = (tid & 3) * 8, n = n0 + r;
+      if (n < g.N) load8(g.B + static_cast<size_t>(n) * g.sbn, 1, k0 + c, ke, v);
+      else for (int i = 0; i < 8; ++i) v[i] = 0;
+      *reinterpret_cast<uint4*>(&Bs[r * kTLd + c]) =
+          uint4{v[0] | (uint32_t(v[1]) << 16), v[2] | (uint32_t(v[3]) << 16), v[4] | (uint32_t(v[5]) << 16),
+                v[6] | (uint32_t(v[7]) << 16)};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kTK; kk += 16) {
+      const int kq = kk + 4 * (lane >> 4);
+      bf16x4 af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        af[i] = *reinterpret_cast<const bf16x4*>(&As[(wm + 16 * i + (lane & 15)) * kTLd + kq]);
+        bf[i] = *reinterpret_cast<const bf16x4*>(&Bs[(wn + 16 * i + (lane & 15)) * kTLd + kq]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout: column lane % 16, rows 4 (lane / 16) + t
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn + 16 * j + (lane & 15);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + t;
+        if (m < g.M && n < g.N) {
+          if (part) part[(static_cast<size_t>(blockIdx.z) * g.M + m) * g.N + n] = acc[i][j][t];
+          else g.C[static_cast<size_t>(m) * g.scm + static_cast<size_t>(n) * g.scn] = acc[i][j][t];
+        }
+      }
+    }
+}
+
+// C(m, n) = sum over the slices in order.
+__global__ void gemm_reduce_kernel(const float* part, int slices, GemmArgs g) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t mn = static_cast<size_t>(g.M) * g.N;
+  if (i >= mn) return;
+  float s = 0.0f;
+#pragma unroll 8
+  for (int z = 0; z < slices; ++z) s += part[z * mn + i];
+  const size_t m = i / g.N, n = i % g.N;
+  g.C[m * g.scm + n * g.scn] = s;
+}
+
 // Z = Y + bias (per column), stored FP32; A = act(Z) stored BF16 (ld columns,
 // padding columns set to zero) and optionally FP32.
 __global__ void bias_act_kernel(BiasActArgs a) {
@@ -398,6 +513,36 @@ hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s) {
 }
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   hipLaunchKernelGGL(gemm_bf16_kernel, dim3((g.M + 15) / 16, (g.N + 15) / 16), dim3(kWave), 0, s, g);
+  return hipGetLastError();
+}
+
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+hipError_t launch_gemm_tiled(const GemmArgs& g, float* part, size_t part_floats, int cus, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
+  const bool ak = g.sak == 1, bn = g.sbn == 1;
+  const bool am = !ak && g.sam == 1, bk = !bn && g.sbk == 1;
+  // the 16-byte loads need 16-byte aligned rows of the contiguous direction
+  const size_t sa = ak ? g.sam : g.sak, sb = bn ? g.sbk : g.sbn;
+  if (!(ak || am) || !(bn || bk) || !aligned16(g.A) || !aligned16(g.B) || (sa % 8) || (sb % 8)) return launch_gemm(g, s);
+  const int tiles = ((g.M + kTM - 1) / kTM) * ((g.N + kTN - 1) / kTN);
+  // split K (the weight gradients: K = rows) until there are about two
+  // work-groups per CU, keeping slices of >= 256 so the reduction stays short
+  int slices = 1;
+  while (tiles * slices < 2 * cus && g.K / (2 * slices) >= 256) slices *= 2;
+  while (slices > 1 && static_cast<size_t>(slices) * g.M * g.N > part_floats) slices /= 2;
+  const int ks = ((g.K + slices - 1) / slices + kTK - 1) / kTK * kTK;
+  slices = (g.K + ks - 1) / ks;
+  float* p = slices > 1 ? part : nullptr;
+  const dim3 grid((g.M + kTM - 1) / kTM, (g.N + kTN - 1) / kTN, slices);
+  if (ak && bn) hipLaunchKernelGGL((gemm_bf16_tiled_kernel<true, true>), grid, dim3(256), 0, s, g, p, ks);
+  else if (ak) hipLaunchKernelGGL((gemm_bf16_tiled_kernel<true, false>), grid, dim3(256), 0, s, g, p, ks);
+  else if (bn) hipLaunchKernelGGL((gemm_bf16_tiled_kernel<false, true>), grid, dim3(256), 0, s, g, p, ks);
+  else hipLaunchKernelGGL((gemm_bf16_tiled_kernel<false, false>), grid, dim3(256), 0, s, g, p, ks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || slices == 1) return e;
+  const size_t mn = static_cast<size_t>(g.M) * g.N;
+  hipLaunchKernelGGL(gemm_reduce_kernel, dim3(nblk(mn, 256)), dim3(256), 0, s, part, slices, g);
   return hipGetLastError();
 }
 hipError_t launch_bias_act(const BiasActArgs& a, hipStream_t s) {

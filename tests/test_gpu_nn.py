@@ -91,6 +91,29 @@ def test_mfma_gemm_exact_on_integer_operands(rows, k, n):
     net.close()
 
 
+@pytest.mark.parametrize("rows,k,n", [(256, 40, 32), (1024, 452, 64), (128, 128, 128)])
+def test_weight_gradient_gemm_exact_on_integer_operands(rows, k, n):
+    """One linear layer with integer data and rows * n a power of two: every
+    value of dY = 2 (Y - T) / (rows n) is exact in BF16 and every sum exact in
+    FP32, so dW = X^T dY and db = sum_rows dY must match bit for bit (the
+    transposed-operand GEMM of the backward pass, split over K)."""
+    print("dW gemm exact", rows, k, n, flush=True)
+    rng = np.random.default_rng(rows + 3 * k + n)
+    X = rng.integers(-2, 3, size=(rows, k)).astype(np.float32)
+    W = rng.integers(-1, 2, size=(k, n)).astype(np.float32)
+    b = rng.integers(-4, 5, size=n).astype(np.float32)
+    T = rng.integers(-4, 5, size=(rows, n)).astype(np.float32)
+    net = dg.Network([k, n], rows)
+    net.set_params(dg.Network.flatten([W, b]))
+    Xd, _ = _x_tensor(X, net.ld)
+    _, g = net.loss_grad(Xd, torch.from_numpy(T).cuda(), want_loss=False, want_grads=True)
+    dY = 2.0 * (X.astype(np.float64) @ W + b - T) / (rows * n)
+    gw, gb = net.unflatten(g)
+    assert np.array_equal(gw.astype(np.float64), X.astype(np.float64).T @ dY)
+    assert np.array_equal(gb.astype(np.float64), dY.sum(axis=0))
+    net.close()
+
+
 SIZES = [452, 128, 128, 128, 64]
 
 

@@ -226,10 +226,37 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   const auto ru = xelem_rsrc(a.fun, xstride, ix, xbytes);
   const auto ro = xelem_rsrc(a.out, xstride, ix, xbytes);
 
+  // v halo through an idle lane: when the chunk leaves lane nact idle and the
+  // v speeds u_ju B of all rows share a sign (zeros aside), that lane fetches
+  // each row's upwind neighbour node (just before or after the chunk, or the
+  // periodic wrap) in the same load instruction as the row, nearly for free;
+  // otherwise the N*N halo values are gathered separately below.
+  bool vpos = false, vneg = false;
+#pragma unroll
+  for (int ju = 0; ju < N; ++ju) {
+    const T av = a.ucoord[iu * N + ju] * a.wc;
+    vpos = vpos || av > T(0);
+    vneg = vneg || av < T(0);
+  }
+  const bool lane_halo = nact < static_cast<unsigned>(kWave) && !(vpos && vneg);
+  unsigned vo_ld = vo;
+  if (lane_halo && lane == nact) {
+    int off;   // nodes relative to the chunk start
+    bool outside;
+    if (vpos) {
+      outside = iv0 == 0;
+      off = outside ? static_cast<int>(NVn) - 1 : -1;
+    } else {
+      outside = iv0 + tva == a.Nv;
+      off = outside ? -static_cast<int>(c0) : static_cast<int>(nact);
+    }
+    vo_ld = (outside && a.zero_inflow) ? kOffOOB : static_cast<unsigned>(off * static_cast<int>(S));
+  }
+
   T f[N][N];
 #pragma unroll
   for (int jx = 0; jx < N; ++jx) {
-    const unsigned vj = vrow(jx, iu);
+    const unsigned vj = vo_ld + ((jx * NUn + iu * N) * NVn + c0) * S;
 #pragma unroll
     for (int ju = 0; ju < N; ++ju) f[jx][ju] = B::ld(rf, vj, ju * rowb);
   }
@@ -272,7 +299,7 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
 
   // v faces: the v speed u B is uniform per u node; one halo value per
   // (x node, u node) row, from the upwind neighbouring v element.
-  for (unsigned h = lane; h < N * N; h += kWave) {
+  for (unsigned h = lane_halo ? N * N : lane; h < N * N; h += kWave) {
     const int jx = h / N, ju = h % N;
     const T av = a.ucoord[iu * N + ju] * a.wc;
     unsigned jv;
@@ -296,6 +323,9 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   const int pv = pact ? lane / N : 0;
   const T sv = pact ? a.Jv * a.ucoord[iu * N + pr] * a.wc : T(0);
   const int hside = (lane < N && a.ucoord[iu * N + lane] * a.wc > T(0)) ? 0 : nact + 1;
+  // column of this lane's value in an LDS row: the halo lane's goes to the
+  // upwind end (slot 0 or nact + 1)
+  const unsigned pcol = (lane_halo && lane == nact && vpos) ? 0u : 1u + lane;
   const double wvl = act ? a.wv[c0 + lane] * a.hu : 0.0;    // v weight times du/2
   const int ntiles = a.Nu * a.nvchunks;
 
@@ -305,7 +335,12 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
 #pragma unroll
     for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld(ru, vrow(0, iu), ju * rowb);
   }
-  T uh = uface(0);
+  // u-face values: without u^n (stage 1) the registers allow fetching all N
+  // of them with the slab; with u^n they are fetched one row ahead
+  constexpr int NUH = UN ? 1 : N;
+  T uhs[NUH];
+#pragma unroll
+  for (int q = 0; q < NUH; ++q) uhs[q] = uface(q);
 
   // LDS: lin holds the current x node's row of f (input of the v pencils),
   // lout[2] the v-axis results of the last two rows (double buffered).
@@ -314,8 +349,8 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   T* const lout1 = lds + 2 * (N + 1) * ROW;
   auto put_row = [&](int jx) {
 #pragma unroll
-    for (int ju = 0; ju < N; ++ju) lin[ju * ROW + 1 + lane] = f[jx][ju];
-    if (lane < N) lin[lane * ROW + hside] = hbuf[jx * N + lane];
+    for (int ju = 0; ju < N; ++ju) lin[ju * ROW + pcol] = f[jx][ju];
+    if (!lane_halo && lane < N) lin[lane * ROW + hside] = hbuf[jx * N + lane];
   };
   // stage combination, store and FP64 density partial of a finished row
   auto finish_row = [&](int jx, const T* acc, const T* lo) {
@@ -381,11 +416,12 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
     {
       const T su = a.Ju * uspeed(jx);
       const bool pos = su > T(0);
+      const T uh = uhs[UN ? 0 : jx];
       const T fL = pos ? uh : f[jx][0];
       const T fR = pos ? f[jx][N - 1] : uh;
       contract<T, N, true>([&](int k) { return f[jx][k]; }, fL, fR, su, acc);
     }
-    if (jx + 1 < N) uh = uface(jx + 1);
+    if (UN && jx + 1 < N) uhs[0] = uface(jx + 1);
     // v axis on the pencil
     {
       const T fL = sv > T(0) ? g[0] : g[1];

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <string>
@@ -365,7 +366,9 @@ dg_status make_ctx(const dg_config* cfg, char* ws, hipStream_t user, bool own_st
   const Layout L = make_layout(cfg);
   dg_ctx* c = new (std::nothrow) dg_ctx();
   if (!c) { *err = "host allocation failed"; return DG_ERR_INVALID; }
+  static std::atomic<uint64_t> next_id{1};
   c->cfg = *cfg;
+  c->id = next_id.fetch_add(1);
   c->L = L;
   c->ws = ws;
   c->user = user;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
 #include <string>
 
 #include "../../include/dg.h"
@@ -24,6 +25,7 @@ struct Layout {
 
 struct dg_ctx {
   dg_config cfg{};
+  uint64_t id = 0;   // unique per context in the process (keys of cached graphs held elsewhere)
   dgi::Layout L;
   dgh::Basis basis;
   double courant = 0.0;

@@ -177,7 +177,7 @@ struct dg_nn {
   std::string err = "no error";
   // cached graph of one corrected coarse step and what it was captured for
   hipGraphExec_t gexec = nullptr;
-  const void* g_ctx = nullptr;
+  uint64_t g_ctx = 0;                 // id of the coarse context it was captured for
   const void* g_f = nullptr;
   const void* g_mean = nullptr;
   const void* g_inv = nullptr;
@@ -667,7 +667,7 @@ dg_status corrected_step(dg_ctx* c, dg_nn* nn, const float* mean, const float* i
 // updates need no new capture: the network's buffers keep their addresses.
 dg_status build_corrected_graph(dg_ctx* c, dg_nn* nn, const float* mean, const float* inv_std, float scale, void* f,
                                 double dt, bool diag) {
-  if (nn->gexec && nn->g_ctx == c && nn->g_f == f && nn->g_mean == mean && nn->g_inv == inv_std && nn->g_dt == dt &&
+  if (nn->gexec && nn->g_ctx == c->id && nn->g_f == f && nn->g_mean == mean && nn->g_inv == inv_std && nn->g_dt == dt &&
       nn->g_scale == scale && nn->g_diag == diag)
     return DG_OK;
   if (nn->gexec) {
@@ -690,7 +690,7 @@ dg_status build_corrected_graph(dg_ctx* c, dg_nn* nn, const float* mean, const f
     nn->gexec = nullptr;
     return dgi::hip_fail(c, e, "hipGraphInstantiate");
   }
-  nn->g_ctx = c;
+  nn->g_ctx = c->id;
   nn->g_f = f;
   nn->g_mean = mean;
   nn->g_inv = inv_std;

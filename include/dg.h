@@ -184,15 +184,22 @@ int32_t dg_batch_grid(const dg_batch* b);
 const char* dg_batch_last_error(const dg_batch* b);
 
 /* ---------- learned coarse-grid correction ----------------------------------
- * A per-element multilayer perceptron corrects the RHS of a coarse 1D2V grid:
- * for every coarse element its input row holds the element's n^3 nodal values,
- * the six face neighbours' n^3 blocks (periodic) and E at its n x nodes
- * (7 n^3 + n features), normalised per feature; the output is an n^3 RHS
- * correction.  Layers are Linear with exact GELU after all but the last;
- * matrix products run on BF16 MFMA with FP32 accumulation, parameters are
- * FP32 masters with BF16 copies, training uses MSE and AdamW.  Fine-grid DG
- * runs generate the training data: f and RHS are L2-projected to the coarse
- * grid and the target is P RHS_fine(f) - RHS_coarse(P f).                  */
+ * A per-element multilayer perceptron corrects the RHS of a coarse 1D2V grid.
+ * Two input forms, told apart by the network's input width:
+ *   7 n^3 + n  whole values: the element's n^3 nodal values, the six face
+ *              neighbours' n^3 blocks (periodic) and E at its n x nodes; the
+ *              correction is made mass-neutral per element;
+ *   8 n^3 + n  fluctuations: the same blocks minus the x average of the
+ *              state (per (u, v) node, LGL-weighted), E, then the element's
+ *              own block of that x average; the correction's x average is
+ *              removed (so the x-averaged distribution and the mass are not
+ *              changed by it).
+ * Features are normalised per column; the output is an n^3 RHS correction.
+ * Layers are Linear with exact GELU after all but the last; matrix products
+ * run on BF16 MFMA with FP32 accumulation, parameters are FP32 masters with
+ * BF16 copies, training uses MSE and AdamW.  Fine-grid DG runs generate the
+ * training data: f and RHS are L2-projected to the coarse grid and the target
+ * is P RHS_fine(f) - RHS_coarse(P f) (minus its x average for fluctuations). */
 
 typedef struct dg_nn dg_nn;
 
@@ -232,22 +239,28 @@ dg_status dg_projection_matrix(int32_t nc, int32_t nf, int32_t r, double* out);
  * waits for it.                                                             */
 dg_status dg_project(dg_ctx* fine, dg_ctx* coarse, const void* f_fine, void* f_coarse);
 /* Network input rows of a coarse FP32 state f with field E (device, Nx*n):
- * (value - mean) * inv_std per feature (device arrays of 7 n^3 + n floats),
- * BF16, one row per element, element order (ix, iu, iv).                   */
+ * (value - mean) * inv_std per feature (device arrays of the network's input
+ * width), BF16, one row per element, element order (ix, iu, iv); the form
+ * (whole / fluctuation) follows the network's input width.  Uses the coarse
+ * context's stage buffers as scratch.                                       */
 dg_status dg_nn_features(dg_ctx* coarse, const dg_nn* nn, const void* f, const double* E, const float* mean,
                          const float* inv_std, uint16_t* X);
-/* Raw (FP32, unnormalised) feature rows, elements x (7 n^3 + n).           */
-dg_status dg_nn_features_raw(dg_ctx* coarse, const void* f, const double* E, float* out);
+/* Raw (FP32, unnormalised) feature rows, elements x (7 n^3 + n), or
+ * elements x (8 n^3 + n) fluctuation features when fluct != 0.             */
+dg_status dg_nn_features_raw(dg_ctx* coarse, const void* f, const double* E, int32_t fluct, float* out);
 /* Element-major copy (elements x n^3) of scale * (x - sub) for coarse
- * state-layout FP32 arrays x and sub (sub may be NULL: scale * x): the
- * training target scale * (P RHS_fine - RHS_coarse(P f)).                  */
-dg_status dg_nn_to_elements(dg_ctx* coarse, const void* x, const void* sub, float scale, float* out);
+ * state-layout FP32 arrays x and sub (sub may be NULL: scale * x), minus its
+ * x average when fluct != 0: the training target.  Uses the coarse context's
+ * stage buffers as scratch.                                                 */
+dg_status dg_nn_to_elements(dg_ctx* coarse, const void* x, const void* sub, float scale, int32_t fluct, float* out);
 /* Per-column sums and sums of squares (host FP64) of a device FP32 matrix.  */
 dg_status dg_nn_column_stats(dg_nn* nn, const float* X, int64_t rows, int32_t cols, double* host_sum, double* host_sumsq);
 /* nsteps SSP-RK3 steps of the coarse grid with RHS L(u) + out_scale * NN(u)
- * at every stage (the correction made mass neutral per element under the
- * LGL product weights), Poisson from each corrected stage state.  f: coarse
- * FP32 state in place.  host_diag as dg_rk_step.                            */
+ * at every stage (whole-value networks: the correction made mass neutral per
+ * element under the LGL product weights; fluctuation networks: its x average
+ * removed), Poisson from each corrected stage state.  f: coarse FP32 state in
+ * place.  host_diag as dg_rk_step.  The step is captured in a HIP graph once
+ * per (context, f, dt, statistics, scale, diag) and replayed.              */
 dg_status dg_nn_rk_step(dg_ctx* coarse, dg_nn* nn, const float* mean, const float* inv_std, float out_scale,
                         void* f, double dt, int32_t nsteps, dg_diag* host_diag);
 const char* dg_nn_last_error(const dg_nn* nn);

@@ -34,7 +34,7 @@ struct NNLayout {
   std::vector<size_t> offW, offb;     // element offsets into the parameter vector
   size_t nparam = 0;
   size_t off_P, off_Pbf, off_G, off_m, off_v, off_Ytmp, off_dA, off_dZ, off_dZb, off_loss, off_sum, off_sumsq,
-      off_Xf, off_Yo, off_corr, off_gpart, total;
+      off_Xf, off_Yo, off_corr, off_xm1, off_xm2, off_gpart, total;
   size_t gpart_floats = 0;   // split-K scratch of the GEMMs
   std::vector<size_t> off_A, off_Z;   // A[l]: BF16 input of layer l (l >= 1); Z[l]: pre-activation of layer l
 };
@@ -87,6 +87,8 @@ NNLayout nn_layout(const int32_t* sizes, int32_t nlayers, int32_t max_rows) {
   N.off_Xf = take(R * N.ld[0] * 2);
   N.off_Yo = take(R * sizes[nlayers] * 4);
   N.off_corr = take(R * sizes[nlayers] * 4);
+  N.off_xm1 = take(R * sizes[nlayers] * 4);
+  N.off_xm2 = take(R * sizes[nlayers] * 4);
   size_t wmm = 0;
   for (int l = 0; l < nlayers; ++l) wmm = std::max(wmm, static_cast<size_t>(sizes[l]) * sizes[l + 1]);
   N.gpart_floats = std::max(4 * R * static_cast<size_t>(N.wmax), 32 * wmm);
@@ -262,22 +264,31 @@ dg_status check_rows(dg_nn* nn, int rows) {
 
 // The coarse grid of a correction must be 1D2V FP32 with n^3 outputs and
 // 7 n^3 + n inputs.
-const char* coarse_mismatch(const dg_ctx* c, const dg_nn* nn) {
+// The coarse grid of a correction must be 1D2V FP32 with n^3 outputs.  Input
+// width 7 n^3 + n: whole values (own block, six neighbour blocks, E); 8 n^3 + n:
+// fluctuation features (the blocks minus the x average of the state, E, then
+// the own block's x average) and an x-mean-free correction.
+const char* coarse_mismatch(const dg_ctx* c, const dg_nn* nn, bool* fluct = nullptr) {
   if (c->cfg.nv != 2) return "the learned correction needs a 1D2V grid";
   if (c->cfg.storage != DG_F32) return "the learned correction needs FP32 storage";
   if (c->cfg.vbc != DG_VBC_PERIODIC) return "the learned correction assumes periodic velocity boundaries";
   if (!nn) return nullptr;
   const int n = c->L.n, nb = n * n * n;
-  if (nn->N.sizes[0] != 7 * nb + n) return "network input width must be 7 n^3 + n";
+  if (nn->N.sizes[0] != 7 * nb + n && nn->N.sizes[0] != 8 * nb + n) return "network input width must be 7 n^3 + n or 8 n^3 + n";
+  if (fluct) *fluct = nn->N.sizes[0] == 8 * nb + n;
   if (nn->N.sizes[nn->N.L] != nb) return "network output width must be n^3";
   const size_t ne = static_cast<size_t>(c->L.Nx) * c->L.Nu * c->L.Nv;
   if (ne > static_cast<size_t>(nn->N.max_rows)) return "coarse element count exceeds max_rows";
   return nullptr;
 }
 
+// values per x node of a coarse state (the inner size of [Nx*n, Nu*n*Nv*n])
+size_t inner_of(const dg_ctx* c) { return static_cast<size_t>(c->L.Nu) * c->L.n * c->L.Nv * c->L.n; }
+
 dgn::GatherArgs gather_args(const dg_ctx* c, const void* f, const double* E, const float* mean, const float* inv_std,
-                            uint16_t* X, int ld) {
+                            uint16_t* X, int ld, const float* xmean) {
   dgn::GatherArgs g{};
+  g.xmean = xmean;
   g.f = static_cast<const float*>(f);
   g.E = E;
   g.mean = mean;
@@ -287,7 +298,7 @@ dgn::GatherArgs gather_args(const dg_ctx* c, const void* f, const double* E, con
   g.Nu = c->L.Nu;
   g.Nv = c->L.Nv;
   g.n = c->L.n;
-  g.nfeat = 7 * c->L.n * c->L.n * c->L.n + c->L.n;
+  g.nfeat = (xmean ? 8 : 7) * c->L.n * c->L.n * c->L.n + c->L.n;
   g.ld = ld;
   return g;
 }
@@ -580,32 +591,61 @@ dg_status dg_nn_features(dg_ctx* coarse, const dg_nn* nn, const void* f, const d
                          const float* inv_std, uint16_t* X) {
   if (!coarse) return DG_ERR_INVALID;
   if (!nn || !f || !E || !mean || !inv_std || !X) return dgi::fail(coarse, DG_ERR_INVALID, "dg_nn_features: NULL argument");
-  if (const char* why = coarse_mismatch(coarse, nn)) return dgi::fail(coarse, DG_ERR_INVALID, why);
+  bool fluct = false;
+  if (const char* why = coarse_mismatch(coarse, nn, &fluct)) return dgi::fail(coarse, DG_ERR_INVALID, why);
   NN_TRY(dgi::enter(coarse));
-  hipError_t e = dgn::launch_gather(gather_args(coarse, f, E, mean, inv_std, X, nn->N.ld[0]), coarse->stream);
+  float* xm = nullptr;
+  hipError_t e = hipSuccess;
+  if (fluct) {   // x average of f into the context's stage scratch
+    xm = coarse->at<float>(coarse->L.off_B);
+    e = dgn::launch_xmean(static_cast<const float*>(f), coarse->at<double>(coarse->L.off_wx), xm, coarse->L.Nx * coarse->L.n,
+                          inner_of(coarse), coarse->stream);
+  }
+  if (e == hipSuccess) e = dgn::launch_gather(gather_args(coarse, f, E, mean, inv_std, X, nn->N.ld[0], xm), coarse->stream);
   if (e != hipSuccess) return dgi::hip_fail(coarse, e, "gather launch");
   return dgi::leave(coarse);
 }
 
-dg_status dg_nn_features_raw(dg_ctx* coarse, const void* f, const double* E, float* out) {
+dg_status dg_nn_features_raw(dg_ctx* coarse, const void* f, const double* E, int32_t fluct, float* out) {
   if (!coarse) return DG_ERR_INVALID;
   if (!f || !E || !out) return dgi::fail(coarse, DG_ERR_INVALID, "dg_nn_features_raw: NULL argument");
   if (const char* why = coarse_mismatch(coarse, nullptr)) return dgi::fail(coarse, DG_ERR_INVALID, why);
   NN_TRY(dgi::enter(coarse));
-  hipError_t e = dgn::launch_gather_raw(gather_args(coarse, f, E, nullptr, nullptr, nullptr, 0), out, coarse->stream);
+  float* xm = nullptr;
+  hipError_t e = hipSuccess;
+  if (fluct) {
+    xm = coarse->at<float>(coarse->L.off_B);
+    e = dgn::launch_xmean(static_cast<const float*>(f), coarse->at<double>(coarse->L.off_wx), xm, coarse->L.Nx * coarse->L.n,
+                          inner_of(coarse), coarse->stream);
+  }
+  if (e == hipSuccess) e = dgn::launch_gather_raw(gather_args(coarse, f, E, nullptr, nullptr, nullptr, 0, xm), out, coarse->stream);
   if (e != hipSuccess) return dgi::hip_fail(coarse, e, "gather launch");
   return dgi::leave(coarse);
 }
 
-dg_status dg_nn_to_elements(dg_ctx* coarse, const void* x, const void* sub, float scale, float* out) {
+dg_status dg_nn_to_elements(dg_ctx* coarse, const void* x, const void* sub, float scale, int32_t fluct, float* out) {
   if (!coarse) return DG_ERR_INVALID;
   if (!x || !out) return dgi::fail(coarse, DG_ERR_INVALID, "dg_nn_to_elements: NULL argument");
   if (const char* why = coarse_mismatch(coarse, nullptr)) return dgi::fail(coarse, DG_ERR_INVALID, why);
+  if (!std::isfinite(scale)) return dgi::fail(coarse, DG_ERR_INVALID, "dg_nn_to_elements: scale must be finite");
   NN_TRY(dgi::enter(coarse));
   const dgi::Layout& L = coarse->L;
-  if (!std::isfinite(scale)) return dgi::fail(coarse, DG_ERR_INVALID, "dg_nn_to_elements: scale must be finite");
-  hipError_t e = dgn::launch_to_elements(static_cast<const float*>(x), static_cast<const float*>(sub), scale, out, L.n, L.Nx,
-                                         L.Nu, L.Nv, coarse->stream);
+  const size_t inner = inner_of(coarse);
+  float* xm = nullptr;
+  hipError_t e = hipSuccess;
+  if (fluct) {   // x average of (x - sub), by linearity mean(x) - mean(sub), in the stage scratch
+    xm = coarse->at<float>(L.off_B);
+    const double* wx = coarse->at<double>(L.off_wx);
+    e = dgn::launch_xmean(static_cast<const float*>(x), wx, xm, L.Nx * L.n, inner, coarse->stream);
+    if (e == hipSuccess && sub) {
+      float* xs = xm + inner;
+      e = dgn::launch_xmean(static_cast<const float*>(sub), wx, xs, L.Nx * L.n, inner, coarse->stream);
+      if (e == hipSuccess) e = dgn::launch_axpy(xm, xs, nullptr, -1.0f, 1, inner, coarse->stream);
+    }
+  }
+  if (e == hipSuccess)
+    e = dgn::launch_to_elements(static_cast<const float*>(x), static_cast<const float*>(sub), xm, scale, out, L.n, L.Nx, L.Nu,
+                                L.Nv, coarse->stream);
   if (e != hipSuccess) return dgi::hip_fail(coarse, e, "to_elements launch");
   return dgi::leave(coarse);
 }
@@ -622,10 +662,18 @@ dg_status corrected_stage(dg_ctx* c, dg_nn* nn, const float* mean, const float* 
   hipStream_t s = c->stream;
   double* E = c->at<double>(L.off_E);
   const int rows = L.Nx * L.Nu * L.Nv;
+  const int nx = L.Nx * L.n;
+  const size_t inner = inner_of(c);
+  bool fluct = false;
+  coarse_mismatch(c, nn, &fluct);
   uint16_t* Xf = nn->at<uint16_t>(nn->N.off_Xf);
   float* Yo = nn->at<float>(nn->N.off_Yo);
   float* corr = nn->at<float>(nn->N.off_corr);
-  hipError_t e = dgn::launch_gather(gather_args(c, fin, E, mean, inv_std, Xf, nn->N.ld[0]), s);
+  float* xm_f = fluct ? nn->at<float>(nn->N.off_xm1) : nullptr;
+  float* xm_c = fluct ? nn->at<float>(nn->N.off_xm2) : nullptr;
+  hipError_t e = hipSuccess;
+  if (fluct) e = dgn::launch_xmean(static_cast<const float*>(fin), c->at<double>(L.off_wx), xm_f, nx, inner, s);
+  if (e == hipSuccess) e = dgn::launch_gather(gather_args(c, fin, E, mean, inv_std, Xf, nn->N.ld[0], xm_f), s);
   if (e != hipSuccess) return dgi::hip_fail(c, e, "gather launch");
   {
     dg_status st = forward_on(nn, Xf, rows, Yo, false, s);
@@ -641,10 +689,15 @@ dg_status corrected_stage(dg_ctx* c, dg_nn* nn, const float* mean, const float* 
   sc.Nv = L.Nv;
   sc.n = L.n;
   sc.ldy = L.n * L.n * L.n;
-  sc.mass_neutral = 1;
+  // whole-value correction: mass-neutral per element; fluctuation correction:
+  // its x average is removed below (which also keeps the total mass)
+  sc.mass_neutral = fluct ? 0 : 1;
   if ((e = dgn::launch_scatter(sc, s)) != hipSuccess) return dgi::hip_fail(c, e, "scatter launch");
+  if (fluct && (e = dgn::launch_xmean(corr, c->at<double>(L.off_wx), xm_c, nx, inner, s)) != hipSuccess)
+    return dgi::hip_fail(c, e, "xmean launch");
   NN_TRY(dgi::stage(c, fin, fun, out, E, nullptr, c_un, c_in, c_dt));
-  if ((e = dgn::launch_axpy(static_cast<float*>(out), corr, static_cast<float>(c_dt), L.dof, s)) != hipSuccess)
+  if ((e = dgn::launch_axpy(static_cast<float*>(out), corr, xm_c, static_cast<float>(c_dt), static_cast<size_t>(nx), inner, s)) !=
+      hipSuccess)
     return dgi::hip_fail(c, e, "axpy launch");
   NN_TRY(dgi::density(c, out));
   return dgi::field(c, E, nullptr, record);

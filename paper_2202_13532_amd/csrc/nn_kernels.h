@@ -21,6 +21,7 @@ struct GatherArgs {
   const float* mean;    // nfeat
   const float* inv_std; // nfeat
   uint16_t* X;          // rows x ld (BF16)
+  const float* xmean;   // x average of f per (u, v) node, or nullptr (whole values)
   int Nx, Nu, Nv, n, nfeat, ld;
 };
 
@@ -78,7 +79,13 @@ hipError_t launch_mse(const float* Y, const float* T, int rows, int cols, int ld
 hipError_t launch_colsum(const float* in, int rows, int cols, float* out, hipStream_t s);
 hipError_t launch_adamw(const AdamArgs& a, hipStream_t s);
 hipError_t launch_colstats(const float* X, size_t rows, int ld, int cols, double* sum, double* sumsq, hipStream_t s);
-hipError_t launch_to_elements(const float* in, const float* sub, float scale, float* out, int n, int Nx, int Nu, int Nv, hipStream_t s);
-hipError_t launch_axpy(float* y, const float* x, float a, size_t n, hipStream_t s);
+// out = scale * (in - sub - xm) element-major (sub, xm optional; xm per (u, v) node)
+hipError_t launch_to_elements(const float* in, const float* sub, const float* xm, float scale, float* out, int n, int Nx,
+                              int Nu, int Nv, hipStream_t s);
+// y += a * (x - xm) (xm optional, per inner index: the state is [outer, inner])
+hipError_t launch_axpy(float* y, const float* x, const float* xm, float a, size_t outer, size_t inner, hipStream_t s);
+// x average of a state [Nx*n, inner] with the x quadrature weights wx (Nx*n,
+// FP64): out[q] = sum_o wx[o] in[o, q] / sum_o wx[o], FP64 sums
+hipError_t launch_xmean(const float* in, const double* wx, float* out, int outer, size_t inner, hipStream_t s);
 
 }  // namespace dgn

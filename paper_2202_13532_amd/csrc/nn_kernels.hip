@@ -107,10 +107,15 @@ __global__ void gather_kernel(GatherArgs a) {
       default: break;
     }
     const int jx = loc / (n * n), ju = (loc / n) % n, jv = loc % n;
-    const size_t idx = ((((static_cast<size_t>(ex) * n + jx) * a.Nu + eu) * n + ju) * a.Nv + ev) * n + jv;
-    val = a.f[idx];
+    const size_t q = ((static_cast<size_t>(eu) * n + ju) * a.Nv + ev) * n + jv;
+    const size_t idx = (static_cast<size_t>(ex) * n + jx) * (static_cast<size_t>(a.Nu) * n * a.Nv * n) + q;
+    val = a.xmean ? a.f[idx] - a.xmean[q] : a.f[idx];
   } else if (col < 7 * nb + n) {
     val = static_cast<float>(a.E[ix * n + (col - 7 * nb)]);
+  } else if (a.xmean && col < 8 * nb + n) {
+    const int loc = col - 7 * nb - n;
+    const int ju = (loc / n) % n, jv = loc % n;
+    val = a.xmean[((static_cast<size_t>(iu) * n + ju) * a.Nv + iv) * n + jv];
   }
   const bool real = col < a.nfeat;
   const float z = real ? (val - a.mean[col]) * a.inv_std[col] : 0.0f;
@@ -435,7 +440,7 @@ __global__ void gather_raw_kernel(GatherArgs a, float* out) {
   const int iv = static_cast<int>(e % a.Nv);
   const int iu = static_cast<int>((e / a.Nv) % a.Nu);
   const int ix = static_cast<int>(e / (static_cast<size_t>(a.Nv) * a.Nu));
-  float val;
+  float val = 0.0f;
   if (col < 7 * nb) {
     const int blk = col / nb, loc = col % nb;
     int ex = ix, eu = iu, ev = iv;
@@ -449,16 +454,23 @@ __global__ void gather_raw_kernel(GatherArgs a, float* out) {
       default: break;
     }
     const int jx = loc / (n * n), ju = (loc / n) % n, jv = loc % n;
-    val = a.f[((((static_cast<size_t>(ex) * n + jx) * a.Nu + eu) * n + ju) * a.Nv + ev) * n + jv];
-  } else {
+    const size_t q = ((static_cast<size_t>(eu) * n + ju) * a.Nv + ev) * n + jv;
+    const size_t idx = (static_cast<size_t>(ex) * n + jx) * (static_cast<size_t>(a.Nu) * n * a.Nv * n) + q;
+    val = a.xmean ? a.f[idx] - a.xmean[q] : a.f[idx];
+  } else if (col < 7 * nb + n) {
     val = static_cast<float>(a.E[ix * n + (col - 7 * nb)]);
+  } else if (a.xmean) {
+    const int loc = col - 7 * nb - n;
+    const int ju = (loc / n) % n, jv = loc % n;
+    val = a.xmean[((static_cast<size_t>(iu) * n + ju) * a.Nv + iv) * n + jv];
   }
   out[tid] = val;
 }
 
-// Element-major copy of scale * (in - sub) (sub optional) for a state-layout
-// array (training targets).
-__global__ void to_elements_kernel(const float* in, const float* sub, float scale, float* out, int n, int Nx, int Nu, int Nv) {
+// Element-major copy of scale * (in - sub - xm) (sub, xm optional) for a
+// state-layout array (training targets; xm per (u, v) node).
+__global__ void to_elements_kernel(const float* in, const float* sub, const float* xm, float scale, float* out, int n, int Nx,
+                                   int Nu, int Nv) {
   const int nb = n * n * n;
   const size_t total = static_cast<size_t>(Nx) * Nu * Nv * nb;
   const size_t tid = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -469,13 +481,32 @@ __global__ void to_elements_kernel(const float* in, const float* sub, float scal
   const int iu = static_cast<int>((e / Nv) % Nu);
   const int ix = static_cast<int>(e / (static_cast<size_t>(Nv) * Nu));
   const int jx = loc / (n * n), ju = (loc / n) % n, jv = loc % n;
-  const size_t src = ((((static_cast<size_t>(ix) * n + jx) * Nu + iu) * n + ju) * Nv + iv) * n + jv;
-  out[tid] = scale * (sub ? in[src] - sub[src] : in[src]);
+  const size_t q = ((static_cast<size_t>(iu) * n + ju) * Nv + iv) * n + jv;
+  const size_t src = (static_cast<size_t>(ix) * n + jx) * (static_cast<size_t>(Nu) * n * Nv * n) + q;
+  float v = sub ? in[src] - sub[src] : in[src];
+  if (xm) v -= xm[q];
+  out[tid] = scale * v;
 }
 
-__global__ void axpy_kernel(float* y, const float* x, float a, size_t n) {
+__global__ void axpy_kernel(float* y, const float* x, const float* xm, float a, size_t outer, size_t inner) {
   const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = __builtin_fmaf(a, x[i], y[i]);
+  if (i >= outer * inner) return;
+  const float v = xm ? x[i] - xm[i % inner] : x[i];
+  y[i] = __builtin_fmaf(a, v, y[i]);
+}
+
+// LGL-weighted average over the outer (x node) index, one thread per inner
+// index, FP64 sum in a fixed order.
+__global__ void xmean_kernel(const float* in, const double* wx, float* out, int outer, size_t inner) {
+  const size_t q = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= inner) return;
+  double s = 0.0, w = 0.0;
+  for (int o = 0; o < outer; ++o) {
+    const double wo = wx[o];
+    s += wo * in[static_cast<size_t>(o) * inner + q];
+    w += wo;
+  }
+  out[q] = static_cast<float>(s / w);
 }
 
 // ---------------------------------------------------------------------------
@@ -570,13 +601,18 @@ hipError_t launch_colstats(const float* X, size_t rows, int ld, int cols, double
   hipLaunchKernelGGL(colstats_kernel, dim3(cols), dim3(256), 0, s, X, rows, ld, sum, sumsq);
   return hipGetLastError();
 }
-hipError_t launch_to_elements(const float* in, const float* sub, float scale, float* out, int n, int Nx, int Nu, int Nv, hipStream_t s) {
+hipError_t launch_to_elements(const float* in, const float* sub, const float* xm, float scale, float* out, int n, int Nx,
+                              int Nu, int Nv, hipStream_t s) {
   const size_t total = static_cast<size_t>(Nx) * Nu * Nv * n * n * n;
-  hipLaunchKernelGGL(to_elements_kernel, dim3(nblk(total, 256)), dim3(256), 0, s, in, sub, scale, out, n, Nx, Nu, Nv);
+  hipLaunchKernelGGL(to_elements_kernel, dim3(nblk(total, 256)), dim3(256), 0, s, in, sub, xm, scale, out, n, Nx, Nu, Nv);
   return hipGetLastError();
 }
-hipError_t launch_axpy(float* y, const float* x, float a, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(axpy_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, y, x, a, n);
+hipError_t launch_axpy(float* y, const float* x, const float* xm, float a, size_t outer, size_t inner, hipStream_t s) {
+  hipLaunchKernelGGL(axpy_kernel, dim3(nblk(outer * inner, 256)), dim3(256), 0, s, y, x, xm, a, outer, inner);
+  return hipGetLastError();
+}
+hipError_t launch_xmean(const float* in, const double* wx, float* out, int outer, size_t inner, hipStream_t s) {
+  hipLaunchKernelGGL(xmean_kernel, dim3(nblk(inner, 256)), dim3(256), 0, s, in, wx, out, outer, inner);
   return hipGetLastError();
 }
 

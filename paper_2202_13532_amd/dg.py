@@ -102,8 +102,8 @@ def lib():
         "dg_projection_matrix": (I, [I, I, I, dp]),
         "dg_project": (I, [P, P, P, P]),
         "dg_nn_features": (I, [P, P, P, P, P, P, P]),
-        "dg_nn_features_raw": (I, [P, P, P, P]),
-        "dg_nn_to_elements": (I, [P, P, P, ctypes.c_float, P]),
+        "dg_nn_features_raw": (I, [P, P, P, I, P]),
+        "dg_nn_to_elements": (I, [P, P, P, ctypes.c_float, I, P]),
         "dg_nn_column_stats": (I, [P, P, ctypes.c_int64, I, dp, dp]),
         "dg_nn_rk_step": (I, [P, P, P, P, ctypes.c_float, P, D, I, diagp]),
         "dg_nn_last_error": (ctypes.c_char_p, [P]),
@@ -491,12 +491,12 @@ def dg_nn_features(coarse_ctx, nn, f, E, mean, inv_std, X):
     _check(lib().dg_nn_features(coarse_ctx, nn, _ptr(f), _ptr(E), _ptr(mean), _ptr(inv_std), _ptr(X)), coarse_ctx)
 
 
-def dg_nn_features_raw(coarse_ctx, f, E, out):
-    _check(lib().dg_nn_features_raw(coarse_ctx, _ptr(f), _ptr(E), _ptr(out)), coarse_ctx)
+def dg_nn_features_raw(coarse_ctx, f, E, out, fluct=False):
+    _check(lib().dg_nn_features_raw(coarse_ctx, _ptr(f), _ptr(E), 1 if fluct else 0, _ptr(out)), coarse_ctx)
 
 
-def dg_nn_to_elements(coarse_ctx, x, sub, scale, out):
-    _check(lib().dg_nn_to_elements(coarse_ctx, _ptr(x), _ptr(sub), float(scale), _ptr(out)), coarse_ctx)
+def dg_nn_to_elements(coarse_ctx, x, sub, scale, out, fluct=False):
+    _check(lib().dg_nn_to_elements(coarse_ctx, _ptr(x), _ptr(sub), float(scale), 1 if fluct else 0, _ptr(out)), coarse_ctx)
 
 
 def dg_nn_rk_step(coarse_ctx, nn, mean, inv_std, out_scale, f, dt, nsteps, diag=False):

@@ -11,10 +11,21 @@ Setting (1D2V, x in [0, 4 pi), v in [-8, 8]^2, omega_c = 1, FP32 storage):
   fine    32^3 elements, n = 8 (16 777 216 DOF)
   coarse  16^3 elements, n = 4 (262 144 DOF, 4096 elements)
   network 452 -> 128 -> 128 -> 128 -> 64 (exact GELU), 99 264 parameters
+          (whole-value form, default); 516 -> ... in the fluctuation form
 Per run r (seed s): a ~ U[0, 1], v_t ~ U[0.7, 1.3] from default_rng(s);
 f0 = a ring(r0 = 3) + (1 - a) Maxwellian(v_t), times 1 + 1e-3 cos(0.5 x).
 A training snapshot of fine state f gives the coarse input P f and the target
 P RHS_fine(f) - RHS_coarse(P f) (per coarse element, n^3 values).
+
+Fluctuation form (Config.fluct): the closure of the x-averaged distribution
+is ~10^3 times larger than that of the perturbation, which is what drives the
+field; a network fitted to the whole target resolves the former and is blind
+to the latter.  In this form the inputs are the blocks of f minus its x
+average (plus the own block of that average), the target is the closure
+minus its x average, and the correction's x average is removed when it is
+applied.  With FP32 right-hand sides the fluctuation closure (~1e-7) is at
+the rounding level of the terms it is computed from, so it is not learnable
+from FP32 data; the whole-value form is the default.
 """
 import math
 import time
@@ -46,6 +57,7 @@ class Config:
     weight_decay: float = 1e-4
     init_seed: int = 12345
     cfl_fraction: float = 0.9
+    fluct: bool = False                # learn the closure of the fluctuation about the x average
 
 
 def run_parameters(seed):
@@ -65,7 +77,7 @@ class LearnedCorrection:
         self.coarse = dg.Solver(2, c.n_coarse, [c.nelem_coarse] * 3, LO, HI, OMEGA_C, device=device)
         n = c.n_coarse
         self.nb = n ** 3
-        self.nfeat = 7 * self.nb + n
+        self.nfeat = (8 if c.fluct else 7) * self.nb + n
         self.ne = c.nelem_coarse ** 3
         self.sizes = [self.nfeat] + list(c.hidden) + [self.nb]
         self.net = dg.Network(self.sizes, self.ne)
@@ -110,7 +122,7 @@ class LearnedCorrection:
         """Element-major target scale * (P RHS_f(f) - RHS_c(P f))."""
         t = self.torch
         out = t.empty((self.ne, self.nb), dtype=t.float32, device=self.device) if out is None else out
-        dg.dg_nn_to_elements(self.coarse.ctx, pair[0], pair[1], float(scale), out)
+        dg.dg_nn_to_elements(self.coarse.ctx, pair[0], pair[1], float(scale), out, self.cfg.fluct)
         return out
 
     def generate(self, seeds, nsnap=None, stride=None, log=None):
@@ -141,7 +153,7 @@ class LearnedCorrection:
         s1 = np.zeros(self.nfeat)
         s2 = np.zeros(self.nfeat)
         for fc, E in zip(states, fields):
-            dg.dg_nn_features_raw(self.coarse.ctx, fc, E, raw)
+            dg.dg_nn_features_raw(self.coarse.ctx, fc, E, raw, self.cfg.fluct)
             a, b = self.net.column_stats(raw)
             s1 += a
             s2 += b

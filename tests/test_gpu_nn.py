@@ -249,14 +249,29 @@ def test_projection_full_size_learned_grids_sampled():
         assert np.max(np.abs(got[ix, :, iu, :, iv, :] - ref)) <= 1e-6 * np.max(np.abs(ref))
 
 
-def _features_np(f, E, n):
+def _xmean_np(f, n):
+    """LGL-weighted average over x (all x elements and nodes) per (u, v) node."""
+    w = lgl.lgl_nodes_weights(n)[1]
+    Nx = f.shape[0]
+    wx = np.tile(w, Nx).reshape(Nx, n, 1, 1, 1, 1)
+    return (f * wx).sum(axis=(0, 1), keepdims=True) / wx.sum()
+
+
+def _features_np(f, E, n, fluct=False):
     """Feature rows by definition: own block, x-1, x+1, u-1, u+1, v-1, v+1
-    neighbour blocks (periodic), then E at the element's x nodes."""
+    neighbour blocks (periodic), then E at the element's x nodes; the
+    fluctuation form uses f minus its x average in the blocks and appends the
+    own block of the x average."""
     Nx, Nu, Nv = f.shape[0], f.shape[2], f.shape[4]
-    B = f.transpose(0, 2, 4, 1, 3, 5).reshape(Nx, Nu, Nv, n ** 3)
+    m = _xmean_np(f, n) if fluct else None
+    g = f - m if fluct else f
+    B = g.transpose(0, 2, 4, 1, 3, 5).reshape(Nx, Nu, Nv, n ** 3)
     parts = [B, np.roll(B, 1, 0), np.roll(B, -1, 0), np.roll(B, 1, 1), np.roll(B, -1, 1),
              np.roll(B, 1, 2), np.roll(B, -1, 2),
              np.broadcast_to(E.reshape(Nx, 1, 1, n), (Nx, Nu, Nv, n))]
+    if fluct:
+        M = np.broadcast_to(m, f.shape).transpose(0, 2, 4, 1, 3, 5).reshape(Nx, Nu, Nv, n ** 3)
+        parts.append(M)
     return np.concatenate(parts, axis=3).reshape(Nx * Nu * Nv, -1)
 
 
@@ -269,7 +284,7 @@ def test_features_raw_normalised_and_elements_exact():
     fd = torch.from_numpy(inputs.random_nodal(s.shape, 3)).float().cuda()
     Ed = torch.from_numpy(inputs.random_field(nelem[0] * n, 3)).cuda()
     raw = torch.empty((ne, nfeat), dtype=torch.float32, device="cuda")
-    dg.dg_nn_features_raw(s.ctx, fd, Ed, raw)
+    dg.dg_nn_features_raw(s.ctx, fd, Ed, raw, False)
     ref = _features_np(fd.cpu().numpy(), Ed.cpu().numpy().astype(np.float32), n)
     assert np.array_equal(raw.cpu().numpy(), ref)
     rng = np.random.default_rng(1)
@@ -284,7 +299,7 @@ def test_features_raw_normalised_and_elements_exact():
     # element-major reordering and target difference
     f2 = torch.from_numpy(inputs.random_nodal(s.shape, 4)).float().cuda()
     el = torch.empty((ne, n ** 3), dtype=torch.float32, device="cuda")
-    dg.dg_nn_to_elements(s.ctx, fd, f2, 1.0, el)
+    dg.dg_nn_to_elements(s.ctx, fd, f2, 1.0, el, False)
     d = (fd - f2).cpu().numpy()
     assert np.array_equal(el.cpu().numpy(), d.transpose(0, 2, 4, 1, 3, 5).reshape(ne, n ** 3))
     # column statistics (FP64 sums)
@@ -295,24 +310,53 @@ def test_features_raw_normalised_and_elements_exact():
     net.close()
 
 
-def _oracle_corrected_rhs(g, ops, u, params, mean, inv, scale, n):
+def test_fluctuation_features_and_targets_match_definition():
+    n, nelem = 4, [5, 3, 4]
+    s = dg.Solver(2, n, nelem, [0.0, -6.0, -6.0], [6.0, 6.0, 6.0], 1.0)
+    ne = 5 * 3 * 4
+    nfeat = 8 * n ** 3 + n
+    fd = torch.from_numpy(inputs.random_nodal(s.shape, 5)).float().cuda()
+    Ed = torch.from_numpy(inputs.random_field(nelem[0] * n, 5)).cuda()
+    raw = torch.empty((ne, nfeat), dtype=torch.float32, device="cuda")
+    dg.dg_nn_features_raw(s.ctx, fd, Ed, raw, True)
+    fh = fd.cpu().numpy().astype(np.float64)
+    ref = _features_np(fh, Ed.cpu().numpy(), n, fluct=True)
+    got = raw.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - ref)) <= 1e-6 * np.max(np.abs(ref))
+    f2 = torch.from_numpy(inputs.random_nodal(s.shape, 6)).float().cuda()
+    el = torch.empty((ne, n ** 3), dtype=torch.float32, device="cuda")
+    dg.dg_nn_to_elements(s.ctx, fd, f2, 2.0, el, True)
+    d = fh - f2.cpu().numpy().astype(np.float64)
+    d = 2.0 * (d - _xmean_np(d, n))
+    want = d.transpose(0, 2, 4, 1, 3, 5).reshape(ne, n ** 3)
+    assert np.max(np.abs(el.cpu().numpy() - want)) <= 1e-6 * np.max(np.abs(want))
+    # the targets have zero x average
+    back = el.cpu().numpy().astype(np.float64).reshape(5, 3, 4, n, n, n).transpose(0, 3, 1, 4, 2, 5)
+    assert np.max(np.abs(_xmean_np(back, n))) <= 1e-6 * np.max(np.abs(want))
+
+
+def _oracle_corrected_rhs(g, ops, u, params, mean, inv, scale, n, fluct=False):
     E = rk.field(g, u)
     Lu = rhs.rhs(g, ops, u, E)
-    Xf = (_features_np(u, E, n) - mean) * inv
+    Xf = (_features_np(u, E, n, fluct) - mean) * inv
     y, _ = mlp.forward(params, Xf)
-    w = lgl.lgl_nodes_weights(n)[1]
-    W = (w[:, None, None] * w[None, :, None] * w[None, None, :]).ravel()
-    y = y - (y @ W / W.sum())[:, None]
     Nx, Nu, Nv = u.shape[0], u.shape[2], u.shape[4]
+    if not fluct:   # mass-neutral per element
+        w = lgl.lgl_nodes_weights(n)[1]
+        W = (w[:, None, None] * w[None, :, None] * w[None, None, :]).ravel()
+        y = y - (y @ W / W.sum())[:, None]
     corr = y.reshape(Nx, Nu, Nv, n, n, n).transpose(0, 3, 1, 4, 2, 5)
+    if fluct:       # x average removed
+        corr = corr - _xmean_np(corr, n)
     return Lu + scale * corr
 
 
+@pytest.mark.parametrize("fluct", [False, True])
 @pytest.mark.parametrize("scale", [0.0, 1.0])
-def test_corrected_step_matches_oracle(scale):
+def test_corrected_step_matches_oracle(scale, fluct):
     n, nelem = 4, [4, 3, 5]
     lo, hi = [0.0, -6.0, -6.0], [4 * math.pi, 6.0, 6.0]
-    print("corrected step", scale, flush=True)
+    print("corrected step", scale, fluct, flush=True)
     s = dg.Solver(2, n, nelem, lo, hi, 1.0)
     g = grid.PhaseGrid(2, n, nelem, lo, hi, 1.0)
     ops = lgl.operators(n)
@@ -321,7 +365,7 @@ def test_corrected_step_matches_oracle(scale):
     fd = torch.from_numpy(f0).float().cuda()
     fh = fd.cpu().numpy().astype(np.float64)
     ne = 4 * 3 * 5
-    nfeat = 7 * n ** 3 + n
+    nfeat = (8 if fluct else 7) * n ** 3 + n
     sizes = [nfeat, 32, 32, n ** 3]
     net = dg.Network(sizes, ne)
     ps = _he_params(sizes, 8)
@@ -330,7 +374,7 @@ def test_corrected_step_matches_oracle(scale):
     ps[-1] = ps[-1] * 0.01
     net.set_params(dg.Network.flatten(ps))
     Eh = rk.field(g, fh)
-    feats = _features_np(fh, Eh, n)
+    feats = _features_np(fh, Eh, n, fluct)
     mean = feats.mean(0).astype(np.float32)
     inv = (1.0 / (feats.std(0) + 1e-3)).astype(np.float32)
     E0 = s.poisson(fd)
@@ -339,7 +383,7 @@ def test_corrected_step_matches_oracle(scale):
     pr = _round_weights(ps)
 
     def Lc(u):
-        return _oracle_corrected_rhs(g, ops, u, pr, mean.astype(np.float64), inv.astype(np.float64), scale, n)
+        return _oracle_corrected_rhs(g, ops, u, pr, mean.astype(np.float64), inv.astype(np.float64), scale, n, fluct)
 
     u1 = fh + dt * Lc(fh)
     u2 = 0.75 * fh + 0.25 * (u1 + dt * Lc(u1))

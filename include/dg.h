@@ -230,9 +230,11 @@ dg_status dg_nn_adamw(dg_nn* nn, float lr, float weight_decay);
  * fine elements with nf LGL nodes inside one coarse element with nc nodes:
  * exact mass matrix and coupling integrals.  nc*r*nf <= 324.                */
 dg_status dg_projection_matrix(int32_t nc, int32_t nf, int32_t r, double* out);
-/* L2 projection of a fine FP32 state (1D1V or 1D2V) onto a nested coarse grid
- * with the same domain (fine element counts multiples of the coarse ones),
- * axis by axis with dg_projection_matrix, FP64 arithmetic, FP32 result.
+/* L2 projection of a fine state (1D1V or 1D2V; FP32 or FP64 storage as the
+ * fine context says) onto a nested coarse grid with the same domain (fine
+ * element counts multiples of the coarse ones), axis by axis with
+ * dg_projection_matrix, FP64 arithmetic, result in the coarse context's
+ * storage precision.
  * Uses the fine context's two stage buffers as scratch (each partial result
  * must fit one of them, else DG_ERR_UNSUPPORTED).  Enqueued on the fine
  * context's stream after both callers' streams; the coarse caller's stream
@@ -248,10 +250,11 @@ dg_status dg_nn_features(dg_ctx* coarse, const dg_nn* nn, const void* f, const d
 /* Raw (FP32, unnormalised) feature rows, elements x (7 n^3 + n), or
  * elements x (8 n^3 + n) fluctuation features when fluct != 0.             */
 dg_status dg_nn_features_raw(dg_ctx* coarse, const void* f, const double* E, int32_t fluct, float* out);
-/* Element-major copy (elements x n^3) of scale * (x - sub) for coarse
- * state-layout FP32 arrays x and sub (sub may be NULL: scale * x), minus its
- * x average when fluct != 0: the training target.  Uses the coarse context's
- * stage buffers as scratch.                                                 */
+/* Element-major FP32 copy (elements x n^3) of scale * (x - sub) for coarse
+ * state-layout arrays x and sub in the coarse context's storage precision
+ * (sub may be NULL: scale * x), minus its x average when fluct != 0: the
+ * training target (with an FP64 context the difference and the average are
+ * taken in FP64).  Uses the coarse context's stage buffers as scratch.      */
 dg_status dg_nn_to_elements(dg_ctx* coarse, const void* x, const void* sub, float scale, int32_t fluct, float* out);
 /* Per-column sums and sums of squares (host FP64) of a device FP32 matrix.  */
 dg_status dg_nn_column_stats(dg_nn* nn, const float* X, int64_t rows, int32_t cols, double* host_sum, double* host_sumsq);

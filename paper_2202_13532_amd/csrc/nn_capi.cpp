@@ -514,7 +514,7 @@ dg_status dg_project(dg_ctx* fine, dg_ctx* coarse, const void* f_fine, void* f_c
   if (!f_fine || !f_coarse) return dgi::fail(coarse, DG_ERR_INVALID, "dg_project: NULL state");
   const dg_config& F = fine->cfg;
   const dg_config& C = coarse->cfg;
-  if (F.storage != DG_F32 || C.storage != DG_F32) return dgi::fail(coarse, DG_ERR_UNSUPPORTED, "dg_project: FP32 storage only");
+  const bool fin32 = F.storage == DG_F32, cout32 = C.storage == DG_F32;
   if (F.nv != C.nv) return dgi::fail(coarse, DG_ERR_INVALID, "dg_project: grids differ in dimension");
   const int naxes = 1 + F.nv;
   int r[3] = {1, 1, 1};
@@ -550,8 +550,9 @@ dg_status dg_project(dg_ctx* fine, dg_ctx* coarse, const void* f_fine, void* f_c
       if (out_count * 8 > cap)
         return dgi::fail(coarse, DG_ERR_UNSUPPORTED, "dg_project: intermediate does not fit the fine stage buffers");
       if (outer > 0x7fffffff || inner > 0x7fffffff) return dgi::fail(coarse, DG_ERR_UNSUPPORTED, "dg_project: grid too large");
-      p.in_f32 = k == 0 ? 1 : 0;
-      p.out = buf[k % 2];
+      p.in_f32 = (k == 0 && fin32) ? 1 : 0;
+      // an FP64 coarse state takes the last axis directly
+      p.out = (k + 1 == order.size() && !cout32) ? static_cast<double*>(f_coarse) : buf[k % 2];
       p.outer = static_cast<int>(outer);
       p.inner = static_cast<int>(inner);
       p.Nc = C.nelem[a];
@@ -576,9 +577,15 @@ dg_status dg_project(dg_ctx* fine, dg_ctx* coarse, const void* f_fine, void* f_c
     if (e != hipSuccess) return dgi::hip_fail(coarse, e, "projection launch");
     in = p.out;
   }
-  hipError_t e = plan.empty()
-                     ? hipMemcpyAsync(f_coarse, f_fine, coarse->L.dof * 4, hipMemcpyDeviceToDevice, s)
-                     : dgn::launch_f64_to_f32(static_cast<const double*>(in), static_cast<float*>(f_coarse), coarse->L.dof, s);
+  hipError_t e = hipSuccess;
+  const size_t dof = coarse->L.dof;
+  if (plan.empty()) {   // identical spaces: a copy, converting the precision if needed
+    if (fin32 == cout32) e = hipMemcpyAsync(f_coarse, f_fine, dof * (cout32 ? 4 : 8), hipMemcpyDeviceToDevice, s);
+    else if (cout32) e = dgn::launch_f64_to_f32(static_cast<const double*>(f_fine), static_cast<float*>(f_coarse), dof, s);
+    else e = dgn::launch_f32_to_f64(static_cast<const float*>(f_fine), static_cast<double*>(f_coarse), dof, s);
+  } else if (cout32) {
+    e = dgn::launch_f64_to_f32(static_cast<const double*>(in), static_cast<float*>(f_coarse), dof, s);
+  }
   if (e != hipSuccess) return dgi::hip_fail(coarse, e, "conversion launch");
   NN_TRY(dgi::leave(fine));
   // the coarse caller's stream orders after the fine stream
@@ -626,26 +633,39 @@ dg_status dg_nn_features_raw(dg_ctx* coarse, const void* f, const double* E, int
 dg_status dg_nn_to_elements(dg_ctx* coarse, const void* x, const void* sub, float scale, int32_t fluct, float* out) {
   if (!coarse) return DG_ERR_INVALID;
   if (!x || !out) return dgi::fail(coarse, DG_ERR_INVALID, "dg_nn_to_elements: NULL argument");
-  if (const char* why = coarse_mismatch(coarse, nullptr)) return dgi::fail(coarse, DG_ERR_INVALID, why);
+  if (coarse->cfg.nv != 2) return dgi::fail(coarse, DG_ERR_INVALID, "the learned correction needs a 1D2V grid");
+  const bool f64 = coarse->cfg.storage == DG_F64;
   if (!std::isfinite(scale)) return dgi::fail(coarse, DG_ERR_INVALID, "dg_nn_to_elements: scale must be finite");
   NN_TRY(dgi::enter(coarse));
   const dgi::Layout& L = coarse->L;
   const size_t inner = inner_of(coarse);
   float* xm = nullptr;
   hipError_t e = hipSuccess;
-  if (fluct) {   // x average of (x - sub), by linearity mean(x) - mean(sub), in the stage scratch
-    xm = coarse->at<float>(L.off_B);
-    const double* wx = coarse->at<double>(L.off_wx);
-    e = dgn::launch_xmean(static_cast<const float*>(x), wx, xm, L.Nx * L.n, inner, coarse->stream);
-    if (e == hipSuccess && sub) {
-      float* xs = xm + inner;
-      e = dgn::launch_xmean(static_cast<const float*>(sub), wx, xs, L.Nx * L.n, inner, coarse->stream);
-      if (e == hipSuccess) e = dgn::launch_axpy(xm, xs, nullptr, -1.0f, 1, inner, coarse->stream);
+  if (f64) {   // FP64 inputs (training targets from FP64 right-hand sides)
+    double* xm64 = nullptr;
+    if (fluct) {
+      xm64 = coarse->at<double>(L.off_B);
+      e = dgn::launch_xmean_diff64(static_cast<const double*>(x), static_cast<const double*>(sub),
+                                   coarse->at<double>(L.off_wx), xm64, L.Nx * L.n, inner, coarse->stream);
     }
+    if (e == hipSuccess)
+      e = dgn::launch_to_elements64(static_cast<const double*>(x), static_cast<const double*>(sub), xm64, scale, out, L.n, L.Nx,
+                                    L.Nu, L.Nv, coarse->stream);
+  } else {
+    if (fluct) {   // x average of (x - sub), by linearity mean(x) - mean(sub), in the stage scratch
+      xm = coarse->at<float>(L.off_B);
+      const double* wx = coarse->at<double>(L.off_wx);
+      e = dgn::launch_xmean(static_cast<const float*>(x), wx, xm, L.Nx * L.n, inner, coarse->stream);
+      if (e == hipSuccess && sub) {
+        float* xs = xm + inner;
+        e = dgn::launch_xmean(static_cast<const float*>(sub), wx, xs, L.Nx * L.n, inner, coarse->stream);
+        if (e == hipSuccess) e = dgn::launch_axpy(xm, xs, nullptr, -1.0f, 1, inner, coarse->stream);
+      }
+    }
+    if (e == hipSuccess)
+      e = dgn::launch_to_elements(static_cast<const float*>(x), static_cast<const float*>(sub), xm, scale, out, L.n, L.Nx, L.Nu,
+                                  L.Nv, coarse->stream);
   }
-  if (e == hipSuccess)
-    e = dgn::launch_to_elements(static_cast<const float*>(x), static_cast<const float*>(sub), xm, scale, out, L.n, L.Nx, L.Nu,
-                                L.Nv, coarse->stream);
   if (e != hipSuccess) return dgi::hip_fail(coarse, e, "to_elements launch");
   return dgi::leave(coarse);
 }

@@ -84,6 +84,12 @@ hipError_t launch_to_elements(const float* in, const float* sub, const float* xm
                               int Nu, int Nv, hipStream_t s);
 // y += a * (x - xm) (xm optional, per inner index: the state is [outer, inner])
 hipError_t launch_axpy(float* y, const float* x, const float* xm, float a, size_t outer, size_t inner, hipStream_t s);
+// FP64 inputs: x average of (x - sub) (sub optional) and the element-major
+// FP32 copy of scale * (in - sub - xm)
+hipError_t launch_xmean_diff64(const double* x, const double* sub, const double* wx, double* out, int outer, size_t inner,
+                               hipStream_t s);
+hipError_t launch_to_elements64(const double* in, const double* sub, const double* xm, float scale, float* out, int n, int Nx,
+                                int Nu, int Nv, hipStream_t s);
 // x average of a state [Nx*n, inner] with the x quadrature weights wx (Nx*n,
 // FP64): out[q] = sum_o wx[o] in[o, q] / sum_o wx[o], FP64 sums
 hipError_t launch_xmean(const float* in, const double* wx, float* out, int outer, size_t inner, hipStream_t s);

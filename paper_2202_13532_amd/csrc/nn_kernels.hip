@@ -488,6 +488,39 @@ __global__ void to_elements_kernel(const float* in, const float* sub, const floa
   out[tid] = scale * v;
 }
 
+// FP64 versions for targets built from FP64 right-hand sides: the x average
+// of (x - sub) in FP64, and the element-major FP32 copy of scale * (x - sub - xm).
+__global__ void xmean_diff64_kernel(const double* x, const double* sub, const double* wx, double* out, int outer, size_t inner) {
+  const size_t q = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= inner) return;
+  double s = 0.0, w = 0.0;
+  for (int o = 0; o < outer; ++o) {
+    const size_t i = static_cast<size_t>(o) * inner + q;
+    s += wx[o] * (sub ? x[i] - sub[i] : x[i]);
+    w += wx[o];
+  }
+  out[q] = s / w;
+}
+
+__global__ void to_elements64_kernel(const double* in, const double* sub, const double* xm, float scale, float* out, int n,
+                                     int Nx, int Nu, int Nv) {
+  const int nb = n * n * n;
+  const size_t total = static_cast<size_t>(Nx) * Nu * Nv * nb;
+  const size_t tid = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (tid >= total) return;
+  const int loc = static_cast<int>(tid % nb);
+  const size_t e = tid / nb;
+  const int iv = static_cast<int>(e % Nv);
+  const int iu = static_cast<int>((e / Nv) % Nu);
+  const int ix = static_cast<int>(e / (static_cast<size_t>(Nv) * Nu));
+  const int jx = loc / (n * n), ju = (loc / n) % n, jv = loc % n;
+  const size_t q = ((static_cast<size_t>(iu) * n + ju) * Nv + iv) * n + jv;
+  const size_t src = (static_cast<size_t>(ix) * n + jx) * (static_cast<size_t>(Nu) * n * Nv * n) + q;
+  double v = sub ? in[src] - sub[src] : in[src];
+  if (xm) v -= xm[q];
+  out[tid] = static_cast<float>(static_cast<double>(scale) * v);
+}
+
 __global__ void axpy_kernel(float* y, const float* x, const float* xm, float a, size_t outer, size_t inner) {
   const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= outer * inner) return;
@@ -609,6 +642,17 @@ hipError_t launch_to_elements(const float* in, const float* sub, const float* xm
 }
 hipError_t launch_axpy(float* y, const float* x, const float* xm, float a, size_t outer, size_t inner, hipStream_t s) {
   hipLaunchKernelGGL(axpy_kernel, dim3(nblk(outer * inner, 256)), dim3(256), 0, s, y, x, xm, a, outer, inner);
+  return hipGetLastError();
+}
+hipError_t launch_xmean_diff64(const double* x, const double* sub, const double* wx, double* out, int outer, size_t inner,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(xmean_diff64_kernel, dim3(nblk(inner, 256)), dim3(256), 0, s, x, sub, wx, out, outer, inner);
+  return hipGetLastError();
+}
+hipError_t launch_to_elements64(const double* in, const double* sub, const double* xm, float scale, float* out, int n, int Nx,
+                                int Nu, int Nv, hipStream_t s) {
+  const size_t total = static_cast<size_t>(Nx) * Nu * Nv * n * n * n;
+  hipLaunchKernelGGL(to_elements64_kernel, dim3(nblk(total, 256)), dim3(256), 0, s, in, sub, xm, scale, out, n, Nx, Nu, Nv);
   return hipGetLastError();
 }
 hipError_t launch_xmean(const float* in, const double* wx, float* out, int outer, size_t inner, hipStream_t s) {

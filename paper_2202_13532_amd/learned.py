@@ -7,9 +7,12 @@ the BF16-MFMA network forward / backward, AdamW and the corrected coarse
 steps.  Host code draws seeds, orders minibatches and turns the per-column
 sums returned by the library into normalisation constants.
 
-Setting (1D2V, x in [0, 4 pi), v in [-8, 8]^2, omega_c = 1, FP32 storage):
-  fine    32^3 elements, n = 8 (16 777 216 DOF)
-  coarse  16^3 elements, n = 4 (262 144 DOF, 4096 elements)
+Setting (1D2V, x in [0, 4 pi), v in [-8, 8]^2, omega_c = 1):
+  fine    32^3 elements, n = 8 (16 777 216 DOF), FP64 storage: it is the
+          reference, and with a 1e-3 perturbation FP32 storage loses the
+          perturbation's accuracy over the ~14 000 fine steps of a run (its
+          field-energy history ends up ~6 % off the FP64 one)
+  coarse  16^3 elements, n = 4 (262 144 DOF, 4096 elements), FP32 storage
   network 452 -> 128 -> 128 -> 128 -> 64 (exact GELU), 99 264 parameters
           (whole-value form, default); 516 -> ... in the fluctuation form
 Per run r (seed s): a ~ U[0, 1], v_t ~ U[0.7, 1.3] from default_rng(s);
@@ -58,6 +61,7 @@ class Config:
     init_seed: int = 12345
     cfl_fraction: float = 0.9
     fluct: bool = False                # learn the closure of the fluctuation about the x average
+    fp64_data: bool = True             # fine runs, projections and both RHS in FP64 (targets then FP32)
 
 
 def run_parameters(seed):
@@ -73,8 +77,12 @@ class LearnedCorrection:
         self.torch = torch
         self.cfg = cfg or Config()
         c = self.cfg
-        self.fine = dg.Solver(2, c.n_fine, [c.nelem_fine] * 3, LO, HI, OMEGA_C, device=device)
+        prec = "f64" if c.fp64_data else "f32"
+        self.fine = dg.Solver(2, c.n_fine, [c.nelem_fine] * 3, LO, HI, OMEGA_C, storage=prec, device=device)
         self.coarse = dg.Solver(2, c.n_coarse, [c.nelem_coarse] * 3, LO, HI, OMEGA_C, device=device)
+        # targets are assembled on a coarse context of the data precision
+        self.coarse_t = (dg.Solver(2, c.n_coarse, [c.nelem_coarse] * 3, LO, HI, OMEGA_C, storage="f64", device=device)
+                         if c.fp64_data else self.coarse)
         n = c.n_coarse
         self.nb = n ** 3
         self.nfeat = (8 if c.fluct else 7) * self.nb + n
@@ -93,11 +101,12 @@ class LearnedCorrection:
         nodes = [t.from_numpy(self.fine.nodes(a)).to(self.device) for a in range(3)]
         x, u, v = inputs.broadcast_coords(nodes, t)
         f = inputs.mixture(x, u, v, p["a"], p["vt"], 0.5, 1e-3, 3.0, t)
-        return f.to(t.float32).contiguous()
+        return f.to(self.fine.dtype).contiguous()
 
-    def project(self, f_fine, out=None):
-        out = self.coarse.empty_state() if out is None else out
-        dg.dg_project(self.fine.ctx, self.coarse.ctx, f_fine, out)
+    def project(self, f_fine, out=None, coarse=None):
+        coarse = self.coarse if coarse is None else coarse
+        out = coarse.empty_state() if out is None else out
+        dg.dg_project(self.fine.ctx, coarse.ctx, f_fine, out)
         return out
 
     def fine_dt(self, f):
@@ -113,8 +122,10 @@ class LearnedCorrection:
         """(coarse state P f, its field, P RHS_f(f), RHS_c(P f)), all coarse state layout."""
         fc = self.project(f)
         rf = self.fine.rhs(f)
-        prf = self.project(rf)
-        rc = self.coarse.rhs(fc)
+        ct = self.coarse_t
+        fct = fc if ct is self.coarse else self.project(f, coarse=ct)
+        prf = self.project(rf, coarse=ct)
+        rc = ct.rhs(fct)
         E = self.coarse.poisson(fc)
         return fc, E, (prf, rc)
 
@@ -122,7 +133,7 @@ class LearnedCorrection:
         """Element-major target scale * (P RHS_f(f) - RHS_c(P f))."""
         t = self.torch
         out = t.empty((self.ne, self.nb), dtype=t.float32, device=self.device) if out is None else out
-        dg.dg_nn_to_elements(self.coarse.ctx, pair[0], pair[1], float(scale), out, self.cfg.fluct)
+        dg.dg_nn_to_elements(self.coarse_t.ctx, pair[0], pair[1], float(scale), out, self.cfg.fluct)
         return out
 
     def generate(self, seeds, nsnap=None, stride=None, log=None):
@@ -321,7 +332,7 @@ class LearnedCorrection:
         return (self.cfg.nelem_coarse * self.cfg.n_coarse) ** 3
 
     def close(self):
-        for o in (self.net, self.fine, self.coarse):
+        for o in (self.net, self.fine, self.coarse, self.coarse_t):
             o.close()
 
 
@@ -336,9 +347,11 @@ def main(argv=None):
     ap.add_argument("--eval-seeds", type=int, nargs="*", default=[1000, 1001])
     ap.add_argument("--coarse-steps", type=int, default=2000)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--fluct", action="store_true", help="fluctuation form (inputs and targets about the x average)")
+    ap.add_argument("--fp32-data", action="store_true", help="fine runs, projections and right-hand sides in FP32")
     a = ap.parse_args(argv)
     cfg = Config(train_seeds=list(range(a.runs)), snapshots_per_run=a.snapshots, snapshot_stride=a.stride,
-                 epochs=a.epochs)
+                 epochs=a.epochs, fluct=a.fluct, fp64_data=not a.fp32_data)
     log = lambda m: print(m, flush=True)  # noqa: E731
     lc = LearnedCorrection(cfg)
     t0 = time.perf_counter()

@@ -8,8 +8,9 @@ epochs) on the real grids (fine 32^3 x n=8, coarse 16^3 x n=4).  Checked:
   this small training set reaches 0.40, the full one 0.13);
 * corrected coarse runs stay finite and conserve mass (the correction is
   mass-neutral per element);
-* the corrected field-energy history stays within 5 % (relative L2) of the
-  fine run's over 250 coarse steps, as does the plain coarse one.
+* against the FP64 fine run, the corrected field-energy history stays within
+  2 % (relative L2) over 250 coarse steps (the bar of the learned-correction
+  workload), as does the plain coarse one.
 """
 import math
 
@@ -46,7 +47,7 @@ def test_learned_correction_trains_and_runs():
     ev = lc.evaluate(1000, 250, checkpoints=2)
     fe = ev["field_energy_rel_l2"]
     print("field energy rel L2", fe, "mass drift", ev["mass_drift"], flush=True)
-    assert fe["coarse_nn"] < 0.05 and fe["plain_coarse"] < 0.05
+    assert fe["coarse_nn"] < 0.02 and fe["plain_coarse"] < 0.02
     assert ev["mass_drift"]["coarse_nn"] < 1e-5
     assert np.all(np.isfinite(ev["history"]["nn"]))
     lc.close()

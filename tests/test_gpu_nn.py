@@ -228,6 +228,30 @@ def test_projection_matches_oracle(case):
         assert np.max(np.abs(got - ref2)) <= 1e-6 * np.max(np.abs(ref2))
 
 
+@pytest.mark.parametrize("fine_st,coarse_st", [("f64", "f64"), ("f64", "f32"), ("f32", "f64")])
+def test_projection_precisions(fine_st, coarse_st):
+    """FP64 states in and out: the projection is FP64 arithmetic throughout."""
+    lo, hi = [0.0, -5.0, -4.0], [3.0, 5.0, 4.0]
+    sf = dg.Solver(2, 8, [4, 4, 6], lo, hi, 1.0, storage=fine_st)
+    sc = dg.Solver(2, 4, [2, 2, 3], lo, hi, 1.0, storage=coarse_st)
+    f = inputs.random_nodal(sf.shape, 9)
+    fd = torch.from_numpy(f).to(device="cuda", dtype=sf.dtype)
+    out = torch.empty(sc.shape, dtype=sc.dtype, device="cuda")
+    dg.dg_project(sf.ctx, sc.ctx, fd, out)
+    ref = projection.project(fd.cpu().numpy().astype(np.float64), 2, 4, 8, 2)
+    tol = 1e-13 if coarse_st == "f64" else 1e-6
+    assert np.max(np.abs(out.cpu().numpy().astype(np.float64) - ref)) <= tol * np.max(np.abs(ref))
+    # FP64 targets: element-major FP32 copy of (x - sub) minus its x average
+    if coarse_st == "f64":
+        x2 = torch.from_numpy(inputs.random_nodal(sc.shape, 10)).cuda()
+        el = torch.empty((2 * 2 * 3, 64), dtype=torch.float32, device="cuda")
+        dg.dg_nn_to_elements(sc.ctx, out, x2, 3.0, el, True)
+        d = out.cpu().numpy() - x2.cpu().numpy()
+        d = 3.0 * (d - _xmean_np(d, 4))
+        want = d.transpose(0, 2, 4, 1, 3, 5).reshape(12, 64)
+        assert np.max(np.abs(el.cpu().numpy() - want)) <= 1e-6 * np.max(np.abs(want))
+
+
 def test_projection_full_size_learned_grids_sampled():
     """Fine 32^3 n=8 -> coarse 16^3 n=4 (the training grids), checked on 64
     sampled coarse elements computed one by one from the fine values."""

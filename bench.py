@@ -64,7 +64,7 @@ def make_state(torch, solver, wl):
     from paper_2202_13532_amd import workloads as W
     nodes = [torch.from_numpy(solver.nodes(a)).cuda() for a in range(1 + wl.nv)]
     f = W.initial_state(wl, nodes, torch)
-    return f.to(solver.dtype).contiguous()
+    return solver.pack(f.to(solver.dtype).contiguous())   # into the solver's state layout
 
 
 def cpu_baseline(wl, budget_s=12.0):
@@ -170,6 +170,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="maxwell_1d2v_n9")
     ap.add_argument("--storage", default=None, help="override storage (f32/f64)")
+    ap.add_argument("--layout", default=None, help="state layout: dense or vpad (1D2V only; the 1D2V default is vpad)")
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -190,7 +191,9 @@ def main():
     if args.storage:
         wl.storage = args.storage
     print("[bench] workload %s storage %s dof %d" % (wl.name, wl.storage, wl.dof()), file=sys.stderr, flush=True)
-    s = dg.Solver(wl.nv, wl.n, wl.nelem, wl.lo, wl.hi, wl.omega_c, 0, wl.storage)
+    # padded v rows (64-value aligned chunks) are the native 1D2V layout
+    layout = args.layout or ("vpad" if wl.nv == 2 else "dense")
+    s = dg.Solver(wl.nv, wl.n, wl.nelem, wl.lo, wl.hi, wl.omega_c, 0, wl.storage, layout=layout)
     f = make_state(torch, s, wl)
     E0 = s.poisson(f)
     maxE = float(E0.abs().max())
@@ -220,7 +223,7 @@ def main():
     bytes_per_launch = [2 * esize * dof, 3 * esize * dof, 3 * esize * dof]
     tot_bytes = sum(bytes_per_launch) * prof.shape[0]
     achieved = tot_bytes / (st_ms.sum() / 1e3) / 1e9
-    traffic_stages = load_traffic(wl.name + "_" + wl.storage)
+    traffic_stages = load_traffic(wl.name + "_" + wl.storage + ("_vpad" if layout == "vpad" else ""))
     # per launch, averaged over the three stage launches like `achieved`
     traffic = sum(traffic_stages) / len(traffic_stages) if traffic_stages else None
     if args.copy_calibration:
@@ -244,7 +247,7 @@ def main():
         "dtype": "f32" if wl.storage == "f32" else "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "dims": "1D%dV" % wl.nv, "n": wl.n, "nelem": wl.nelem,
-                   "dof": dof, "omega_c": wl.omega_c, "dt": dt, "storage": wl.storage,
+                   "dof": dof, "omega_c": wl.omega_c, "dt": dt, "storage": wl.storage, "layout": layout,
                    "reductions": "f64", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

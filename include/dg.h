@@ -22,7 +22,8 @@
  *
  * Conventions shared by every call:
  *   - State layout (Sec. 3.1): dense row-major [Nx, n, Nu, n, Nv, n] for 1D2V
- *     and [Nx, n, Nv, n] for 1D1V: element index then node index per axis.
+ *     and [Nx, n, Nv, n] for 1D1V: element index then node index per axis
+ *     (1D2V may pad the v rows instead: DG_LAYOUT_VPAD below).
  *     Element m of an axis spans [lo + m dx, lo + (m+1) dx]; node j sits at
  *     lo + (m + 1/2) dx + xi_j dx / 2 with xi_j the ascending LGL nodes.
  *   - Every array pointer passed to a compute call is a DEVICE pointer owned
@@ -66,6 +67,22 @@ typedef enum { DG_F32 = 0, DG_F64 = 1 } dg_dtype;
  * inflow (the value beyond a velocity edge is 0).  x is always periodic.    */
 typedef enum { DG_VBC_PERIODIC = 0, DG_VBC_ZERO_INFLOW = 1 } dg_vbc;
 
+/* State layouts (dg_config.layout).
+ *   DG_LAYOUT_DENSE: the dense row-major arrays described above.
+ *   DG_LAYOUT_VPAD (1D2V only): the same order of rows, but each row of
+ *     Nv*n v values (one x node, one u node) is stored as C = ceil(Nv / TV)
+ *     chunks of 64 values, TV = floor(64 / n): chunk c holds the values of v
+ *     elements [c TV, min(c TV + TV, Nv)) followed by unused slots, so every
+ *     chunk starts on a 64-value boundary (256 bytes in FP32) and each
+ *     64-lane load or store of the stage kernel covers whole aligned memory
+ *     lines.  A row holds 64 C values and a state dg_state_elems() values.
+ *     Unused slots never influence a result; dg_state_pack fills them with
+ *     zeros and every call that writes a state writes zeros there (whole
+ *     memory lines are cheaper to write than partial ones).  For n = 2, 4, 8
+ *     and Nv a multiple of TV the two layouts coincide.
+ * The learned-correction and projection calls accept only DG_LAYOUT_DENSE. */
+typedef enum { DG_LAYOUT_DENSE = 0, DG_LAYOUT_VPAD = 1 } dg_layout;
+
 typedef struct {
   int32_t nv;        /* velocity dimensions: 1 (1D1V) or 2 (1D2V)               */
   int32_t n;         /* LGL nodes per element per axis, 2..9                     */
@@ -76,7 +93,7 @@ typedef struct {
   int32_t pmax;      /* Fourier modes kept, 0..2048; 0 selects nelem[0] (Sec. 5.3.1) */
   int32_t storage;   /* dg_dtype of f                                             */
   int32_t vbc;       /* dg_vbc                                                    */
-  int32_t reserved;  /* must be 0                                                 */
+  int32_t layout;    /* dg_layout of every state array of the context            */
 } dg_config;
 
 /* One diagnostics record (FP64).  mass = int f, field_energy = 1/2 int E^2 dx
@@ -145,6 +162,17 @@ dg_status dg_node_coords(const dg_ctx* ctx, int32_t axis, double* host_out);
 /* Message of the last error on ctx (or of the last failed dg_init when ctx
  * is NULL).  Never NULL.                                                    */
 const char* dg_last_error(const dg_ctx* ctx);
+
+/* Values (of the storage dtype) in one state array of ctx's layout: the DOF
+ * count for DG_LAYOUT_DENSE, Nx n Nu n 64 C for DG_LAYOUT_VPAD.  Host-only.  */
+size_t dg_state_elems(const dg_ctx* ctx);
+
+/* Layout conversion on the context's stream (device arrays of the storage
+ * dtype, not overlapping): dg_state_pack writes the dense array `dense` (DOF
+ * values) into `state` (dg_state_elems() values, zeros in unused slots);
+ * dg_state_unpack is its inverse.  For DG_LAYOUT_DENSE both are copies.    */
+dg_status dg_state_pack(dg_ctx* ctx, const void* dense, void* state);
+dg_status dg_state_unpack(dg_ctx* ctx, const void* state, void* dense);
 
 /* ---------- batched runs (many independent, uneven runs in one launch) ---- */
 

@@ -42,7 +42,8 @@ const char* validate(const dg_config* c) {
   if (c->pmax < 0 || c->pmax > 2048) return "pmax must be in 0..2048";
   if (c->storage != DG_F32 && c->storage != DG_F64) return "storage must be DG_F32 or DG_F64";
   if (c->vbc != DG_VBC_PERIODIC && c->vbc != DG_VBC_ZERO_INFLOW) return "vbc must be DG_VBC_PERIODIC or DG_VBC_ZERO_INFLOW";
-  if (c->reserved != 0) return "reserved must be 0";
+  if (c->layout != DG_LAYOUT_DENSE && c->layout != DG_LAYOUT_VPAD) return "layout must be DG_LAYOUT_DENSE or DG_LAYOUT_VPAD";
+  if (c->layout == DG_LAYOUT_VPAD && c->nv != 2) return "DG_LAYOUT_VPAD needs nv == 2";
   return nullptr;
 }
 
@@ -60,11 +61,15 @@ Layout make_layout(const dg_config* c) {
   L.nvchunks = (L.Nv + tv - 1) / tv;
   L.ntiles_slab = L.Nu * L.nvchunks;
   L.ntiles = L.Nx * L.ntiles_slab;
+  const bool vpad = c->layout == DG_LAYOUT_VPAD;
+  L.cpitch = vpad ? dgk::kWave : tv * L.n;
+  L.lpitch = vpad ? L.nvchunks * dgk::kWave : L.Nv * L.n;
+  L.selems = vpad ? static_cast<size_t>(L.Nx) * L.n * L.Nu * L.n * L.lpitch : L.dof;
   const size_t nx = static_cast<size_t>(L.Nx) * L.n;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
-  L.off_B = take(L.dof * L.esize);
-  L.off_C = take(L.dof * L.esize);
+  L.off_B = take(L.selems * L.esize);
+  L.off_C = take(L.selems * L.esize);
   L.off_part = take(nx * L.ntiles_slab * 8);
   L.off_mom = take(static_cast<size_t>(L.ntiles) * 4 * 8);
   L.off_dens = take(nx * 8);
@@ -169,6 +174,8 @@ void fill_pack(const dg_ctx* c, dgk::StageArgs<T>* p, const void* fin, const voi
   a.Nu = L.Nu;
   a.Nv = L.Nv;
   a.nvchunks = L.nvchunks;
+  a.cpitch = L.cpitch;
+  a.lpitch = L.lpitch;
   a.zero_inflow = c->cfg.vbc == DG_VBC_ZERO_INFLOW ? 1 : 0;
   a.Jx = static_cast<T>(2.0 / c->dx[0]);
   if (c->cfg.nv == 2) {
@@ -345,6 +352,22 @@ void copy_record(const double* r, double t, dg_diag* out) {
 
 using namespace dgi;
 
+namespace {
+
+// dense <-> context layout (Layout::cpitch / lpitch), on the context stream
+dg_status repack_state(dg_ctx* ctx, bool pack, const void* in, void* out) {
+  if (!ctx) return DG_ERR_INVALID;
+  if (!in || !out) return fail(ctx, DG_ERR_INVALID, pack ? "dg_state_pack: NULL array" : "dg_state_unpack: NULL array");
+  const Layout& L = ctx->L;
+  DG_TRY(enter(ctx));
+  const hipError_t e = dgk::launch_repack(pack, L.esize == 8, in, out, L.selems / L.lpitch, L.lpitch, L.cpitch,
+                                          dgk::tv_of(L.n) * L.n, L.Nv * L.n, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "layout conversion launch");
+  return leave(ctx);
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t dg_workspace_bytes(const dg_config* cfg) {
@@ -452,7 +475,7 @@ const char* check_cfg(const dg_config* cfg, dg_status* st) {
   const Layout L = make_layout(cfg);
   if (L.ntiles <= 0 || static_cast<long long>(L.Nx) * L.ntiles_slab > 0x7fffffffLL) return "grid too large";
   // one x element must be addressable by a 31-bit buffer offset
-  if (static_cast<double>(L.dof) / L.Nx * L.esize >= 2147483648.0) return "x element larger than 2 GiB";
+  if (static_cast<double>(L.selems) / L.Nx * L.esize >= 2147483648.0) return "x element larger than 2 GiB";
   *st = DG_OK;
   return nullptr;
 }
@@ -518,6 +541,12 @@ dg_status dg_poisson(dg_ctx* ctx, const void* f, double* E, double* coeffs) {
   DG_TRY(field(ctx, E, coeffs, false));
   return leave(ctx);
 }
+
+size_t dg_state_elems(const dg_ctx* ctx) { return ctx ? ctx->L.selems : 0; }
+
+dg_status dg_state_pack(dg_ctx* ctx, const void* dense, void* state) { return repack_state(ctx, true, dense, state); }
+
+dg_status dg_state_unpack(dg_ctx* ctx, const void* state, void* dense) { return repack_state(ctx, false, state, dense); }
 
 double dg_dt_max(const dg_ctx* ctx, double max_abs_E) {
   if (!ctx) return 0.0;

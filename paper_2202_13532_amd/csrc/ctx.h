@@ -17,6 +17,8 @@ struct Layout {
   size_t esize = 0, dof = 0;
   int naxes = 0, n = 0, Nx = 0, Nu = 1, Nv = 0, nvchunks = 0, pmax = 0;
   int ntiles_slab = 0, ntiles = 0;
+  int cpitch = 0, lpitch = 0;   // values per v chunk and per row of a state array (dg_layout)
+  size_t selems = 0;            // values in a state array
   size_t off_B, off_C, off_part, off_mom, off_dens, off_E, off_cpart, off_mpart, off_coef, off_ring,
       off_last, off_ctr, off_T, off_z1, off_wx, off_wu, off_wv, off_uc, off_vc, off_uc64, off_vc64, total;
 };

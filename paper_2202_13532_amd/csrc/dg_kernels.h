@@ -30,6 +30,7 @@ struct StageArgs {
   double* partials;       // density partials or nullptr
   double hu;              // du/2 (u-axis Jacobian inverse), nv = 2
   int Nx, Nu, Nv, nvchunks;
+  int cpitch, lpitch;     // values per v chunk / per (x node, u node) row of the arrays
   int zero_inflow;        // 1: zero outside the velocity box
   T Jx, Ju, Jv, wc;       // Jacobians 2/dx per axis, omega_c
   T c_un, c_in, c_dt;     // stage coefficients
@@ -62,6 +63,10 @@ hipError_t launch_moments(int nv, int n, bool f64, const void* args, double* mom
 hipError_t launch_field(const FieldArgs& a, hipStream_t s);
 hipError_t launch_moments_reduce(const double* mom, int ntiles, double* ring, const int* counter, hipStream_t s);
 hipError_t launch_reset_counter(int* counter, hipStream_t s);
+// dense rows of nvn values <-> rows of lp values in chunks of cp (tvn used);
+// pack writes rows*lp values (zeros in unused slots), unpack rows*nvn
+hipError_t launch_repack(bool pack, bool f64, const void* in, void* out, size_t rows, unsigned lp, unsigned cp,
+                         unsigned tvn, unsigned nvn, hipStream_t s);
 
 // Batched persistent stage of one kind (n, nv): `runs` (device) holds one
 // StageArgs<float> per run of the batch, `items` (device) the kind's (run,

@@ -17,6 +17,8 @@
 //   so the flux contraction is the speed times the contraction of f.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dg_kernels.h"
 #include "dg_ops_constexpr.h"
 
@@ -187,7 +189,10 @@ template <int N>
 constexpr int lds_words_1v() { return (N + 1) * lds_row<N>(); }
 
 // -------------------------------------------------------------------------
-// 1D2V stage kernel.  state [Nx, N, Nu, N, Nv, N].  UN: stage reads u^n.
+// 1D2V stage kernel.  state [Nx, N, Nu, N, rows of lpitch values]: a row
+// holds the Nv*N v values (one x node, one u node) as nvchunks chunks of TV
+// elements, chunk c starting at position c*cpitch (cpitch = TV*N dense, 64
+// padded).  UN: stage reads u^n.
 // -------------------------------------------------------------------------
 // lds: lds_words_2v<N>() words (input rows + 2 result buffers; row N of each
 // is the scratch row of idle lanes); hbuf: N*N words.
@@ -209,19 +214,29 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   const unsigned nact = tva * N;
   const bool act = lane < nact;
   const unsigned vo = act ? lane * S : kOffOOB;
-  const unsigned NVn = static_cast<unsigned>(a.Nv) * N;
   const unsigned NUn = static_cast<unsigned>(a.Nu) * N;
-  const size_t xstride = static_cast<size_t>(N) * NUn * NVn;   // values per x element
+  const unsigned LP = static_cast<unsigned>(a.lpitch);          // values per row (v line) in memory
+  const unsigned CP = static_cast<unsigned>(a.cpitch);          // values per v chunk in memory
+  const size_t xstride = static_cast<size_t>(N) * NUn * LP;     // values per x element
   const unsigned xbytes = static_cast<unsigned>(xstride * S);
   const unsigned c0 = iv0 * N;                                  // first v node of the chunk
+  const unsigned m0 = vc * CP;                                  // its position in a row
+  const unsigned gap = CP - TV * N;                             // unused slots after a full chunk
+  // position of the row's last v node (end of the last, possibly ragged, chunk)
+  const unsigned mlast = (a.nvchunks - 1) * CP + (a.Nv - (a.nvchunks - 1) * TV) * N - 1;
   // byte offset of (row (jx, iu', ju), chunk start) inside one x element
-  auto soff = [&](int jx, int iue, int ju) -> unsigned { return ((jx * NUn + iue * N + ju) * NVn + c0) * S; };
+  auto soff = [&](int jx, int iue, int ju) -> unsigned { return ((jx * NUn + iue * N + ju) * LP + m0) * S; };
   // Rows (jx, iu, 0..N-1) are rowb bytes apart: their common part goes in the
   // lane offset (one VALU add per x node; idle lanes stay out of range) and
   // ju * rowb in the scalar offset, so only N distinct scalar offsets are live
   // instead of one per row of the slab.
-  const unsigned rowb = NVn * S;
-  auto vrow = [&](int jx, int iue) -> unsigned { return vo + ((jx * NUn + iue * N) * NVn + c0) * S; };
+  const unsigned rowb = LP * S;
+  auto vrow = [&](int jx, int iue) -> unsigned { return vo + ((jx * NUn + iue * N) * LP + m0) * S; };
+  // Store offset: the active lanes, plus the unused slots that end a padded
+  // chunk, which receive zeros, so that every memory line of a row is written
+  // whole (a line left partly written costs the memory a read-modify-write).
+  // For dense rows this is exactly the active lanes.
+  const unsigned vs = (lane < CP && m0 + lane < LP) ? lane * S : kOffOOB;
   const auto rf = xelem_rsrc(a.fin, xstride, ix, xbytes);
   const auto ru = xelem_rsrc(a.fun, xstride, ix, xbytes);
   const auto ro = xelem_rsrc(a.out, xstride, ix, xbytes);
@@ -241,14 +256,14 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   const bool lane_halo = nact < static_cast<unsigned>(kWave) && !(vpos && vneg);
   unsigned vo_ld = vo;
   if (lane_halo && lane == nact) {
-    int off;   // nodes relative to the chunk start
+    int off;   // row positions relative to the chunk start
     bool outside;
     if (vpos) {
       outside = iv0 == 0;
-      off = outside ? static_cast<int>(NVn) - 1 : -1;
+      off = outside ? static_cast<int>(mlast) : -static_cast<int>(gap) - 1;
     } else {
       outside = iv0 + tva == a.Nv;
-      off = outside ? -static_cast<int>(c0) : static_cast<int>(nact);
+      off = outside ? -static_cast<int>(m0) : static_cast<int>(CP);
     }
     vo_ld = (outside && a.zero_inflow) ? kOffOOB : static_cast<unsigned>(off * static_cast<int>(S));
   }
@@ -256,7 +271,7 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   T f[N][N];
 #pragma unroll
   for (int jx = 0; jx < N; ++jx) {
-    const unsigned vj = vo_ld + ((jx * NUn + iu * N) * NVn + c0) * S;
+    const unsigned vj = vo_ld + ((jx * NUn + iu * N) * LP + m0) * S;
 #pragma unroll
     for (int ju = 0; ju < N; ++ju) f[jx][ju] = B::ld(rf, vj, ju * rowb);
   }
@@ -302,17 +317,16 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   for (unsigned h = lane_halo ? N * N : lane; h < N * N; h += kWave) {
     const int jx = h / N, ju = h % N;
     const T av = a.ucoord[iu * N + ju] * a.wc;
-    unsigned jv;
+    unsigned jv;   // row position of the upwind neighbour node
     bool outside;
     if (av > T(0)) {
       outside = iv0 == 0;
-      jv = outside ? NVn - 1 : c0 - 1;
+      jv = outside ? mlast : m0 - gap - 1;
     } else {
-      const int e = iv0 + tva;
-      outside = e == a.Nv;
-      jv = outside ? 0u : static_cast<unsigned>(e) * N;
+      outside = iv0 + tva == a.Nv;
+      jv = outside ? 0u : m0 + CP;
     }
-    const T val = B::ld(rf, ((jx * NUn + iu * N + ju) * NVn + jv) * S, 0u);
+    const T val = B::ld(rf, ((jx * NUn + iu * N + ju) * LP + jv) * S, 0u);
     hbuf[h] = (av == T(0) || (outside && a.zero_inflow)) ? T(0) : val;
   }
 
@@ -323,6 +337,11 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   const int pv = pact ? lane / N : 0;
   const T sv = pact ? a.Jv * a.ucoord[iu * N + pr] * a.wc : T(0);
   const int hside = (lane < N && a.ucoord[iu * N + lane] * a.wc > T(0)) ? 0 : nact + 1;
+  // upwind side of the pencil's faces.  It follows the halo slot that is
+  // written: with the idle-lane halo only the tile's upwind slot holds data,
+  // so a row with zero speed reads that side too (its flux is 0 * t, and t
+  // must be finite: the other slot holds whatever LDS held before).
+  const bool vleft = pact && (lane_halo ? vpos : a.ucoord[iu * N + pr] * a.wc > T(0));
   // column of this lane's value in an LDS row: the halo lane's goes to the
   // upwind end (slot 0 or nact + 1)
   const unsigned pcol = (lane_halo && lane == nact && vpos) ? 0u : 1u + lane;
@@ -373,10 +392,10 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
     }
     // density partial: (du/2) sum_ju w_ju v, reference weights as literals
     double sum = 0.0;
-    const unsigned vj = vrow(jx, iu);
+    const unsigned vj = vs + ((jx * NUn + iu * N) * LP + m0) * S;
 #pragma unroll
     for (int ju = 0; ju < N; ++ju) {
-      B::st(vout[ju], ro, vj, ju * rowb);
+      B::st(act ? vout[ju] : T(0), ro, vj, ju * rowb);
       sum = __builtin_fma(K.w[ju], static_cast<double>(vout[ju]), sum);
     }
     if (a.partials) {
@@ -424,8 +443,8 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
     if (UN && jx + 1 < N) uhs[0] = uface(jx + 1);
     // v axis on the pencil
     {
-      const T fL = sv > T(0) ? g[0] : g[1];
-      const T fR = sv > T(0) ? g[N] : g[N + 1];
+      const T fL = vleft ? g[0] : g[1];
+      const T fR = vleft ? g[N] : g[N + 1];
       T r[N];
       contract<T, N, false>([&](int k) { return g[k + 1]; }, fL, fR, sv, r);
       T* lo = (jx & 1) ? lout1 : lout0;
@@ -571,9 +590,9 @@ __global__ void __launch_bounds__(kWave) density_kernel(StageArgs<T> a) {
   const int tva = min(TV, a.Nv - iv0);
   const bool act = lane < tva * N;
   const int jl = act ? lane : 0;
-  const size_t NVn = static_cast<size_t>(a.Nv) * N;
+  const size_t LP = static_cast<size_t>(a.lpitch);   // row pitch
   const size_t NUn = static_cast<size_t>(NV == 2 ? a.Nu : 1) * N;
-  const T* __restrict__ fin = a.fin + static_cast<size_t>(iv0) * N + jl;
+  const T* __restrict__ fin = a.fin + static_cast<size_t>(vc) * a.cpitch + jl;
   const double wvl = act ? a.wv[iv0 * N + jl] : 0.0;
   const int ntiles = (NV == 2 ? a.Nu : 1) * a.nvchunks;
 #pragma unroll
@@ -582,14 +601,39 @@ __global__ void __launch_bounds__(kWave) density_kernel(StageArgs<T> a) {
     if (NV == 2) {
 #pragma unroll
       for (int ju = 0; ju < N; ++ju) {
-        const size_t r = ((static_cast<size_t>(ix) * N + jx) * NUn + static_cast<size_t>(iu) * N + ju) * NVn;
+        const size_t r = ((static_cast<size_t>(ix) * N + jx) * NUn + static_cast<size_t>(iu) * N + ju) * LP;
         s = __builtin_fma(a.wu[iu * N + ju], static_cast<double>(fin[r]), s);
       }
     } else {
-      s = static_cast<double>(fin[(static_cast<size_t>(ix) * N + jx) * NVn]);
+      s = static_cast<double>(fin[(static_cast<size_t>(ix) * N + jx) * LP]);
     }
     s = wave_sum(act ? s * wvl : 0.0);
     if (lane == 0) a.partials[static_cast<size_t>(ix * N + jx) * ntiles + iu * a.nvchunks + vc] = s;
+  }
+}
+
+// Layout conversion between a dense state (rows of nvn values) and one
+// with rows of lp values holding chunks of cp values, the first tvn used.
+template <typename T>
+__global__ void pack_rows_kernel(const T* __restrict__ dense, T* __restrict__ out, size_t total, unsigned lp,
+                                 unsigned cp, unsigned tvn, unsigned nvn) {
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const size_t row = i / lp;
+    const unsigned m = static_cast<unsigned>(i - row * lp);
+    const unsigned c = m / cp, k = m - c * cp, node = c * tvn + k;
+    out[i] = (k < tvn && node < nvn) ? dense[row * nvn + node] : T(0);
+  }
+}
+template <typename T>
+__global__ void unpack_rows_kernel(const T* __restrict__ in, T* __restrict__ dense, size_t total, unsigned lp,
+                                   unsigned cp, unsigned tvn, unsigned nvn) {
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const size_t row = i / nvn;
+    const unsigned node = static_cast<unsigned>(i - row * nvn);
+    const unsigned c = node / tvn;
+    dense[i] = in[row * lp + c * cp + (node - c * tvn)];
   }
 }
 
@@ -609,9 +653,9 @@ __global__ void __launch_bounds__(kWave) moments_kernel(StageArgs<T> a, double* 
   const int tva = min(TV, a.Nv - iv0);
   const bool act = lane < tva * N;
   const int jl = act ? lane : 0;
-  const size_t NVn = static_cast<size_t>(a.Nv) * N;
+  const size_t LP = static_cast<size_t>(a.lpitch);   // row pitch
   const size_t NUn = static_cast<size_t>(NV == 2 ? a.Nu : 1) * N;
-  const T* __restrict__ fin = a.fin + static_cast<size_t>(iv0) * N + jl;
+  const T* __restrict__ fin = a.fin + static_cast<size_t>(vc) * a.cpitch + jl;
   const double wvl = act ? a.wv[iv0 * N + jl] : 0.0;
   const double v = a.vc64[iv0 * N + jl];
   double m = 0.0, k = 0.0, l2 = 0.0, bad = 0.0;
@@ -619,8 +663,8 @@ __global__ void __launch_bounds__(kWave) moments_kernel(StageArgs<T> a, double* 
     const double wxv = a.wx[ix * N + jx];
     for (int ju = 0; ju < NU; ++ju) {
       const size_t r = NV == 2
-          ? ((static_cast<size_t>(ix) * N + jx) * NUn + static_cast<size_t>(iu) * N + ju) * NVn
-          : (static_cast<size_t>(ix) * N + jx) * NVn;
+          ? ((static_cast<size_t>(ix) * N + jx) * NUn + static_cast<size_t>(iu) * N + ju) * LP
+          : (static_cast<size_t>(ix) * N + jx) * LP;
       const double fv = act ? static_cast<double>(fin[r]) : 0.0;
       const double wuv = NV == 2 ? a.wu[iu * N + ju] : 1.0;
       const double u = NV == 2 ? a.uc64[iu * N + ju] : 0.0;
@@ -1035,6 +1079,21 @@ hipError_t launch_field_batched(const FieldArgs* fa, const int2* xitems, int nxi
 
 hipError_t launch_reset_counter(int* counter, hipStream_t s) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_repack(bool pack, bool f64, const void* in, void* out, size_t rows, unsigned lp, unsigned cp,
+                         unsigned tvn, unsigned nvn, hipStream_t s) {
+  const size_t total = rows * (pack ? lp : nvn);
+  if (total == 0) return hipSuccess;
+  const unsigned grid = static_cast<unsigned>(std::min<size_t>((total + 255) / 256, 65536));
+  if (pack) {
+    if (f64) hipLaunchKernelGGL(pack_rows_kernel<double>, dim3(grid), dim3(256), 0, s, static_cast<const double*>(in), static_cast<double*>(out), total, lp, cp, tvn, nvn);
+    else hipLaunchKernelGGL(pack_rows_kernel<float>, dim3(grid), dim3(256), 0, s, static_cast<const float*>(in), static_cast<float*>(out), total, lp, cp, tvn, nvn);
+  } else {
+    if (f64) hipLaunchKernelGGL(unpack_rows_kernel<double>, dim3(grid), dim3(256), 0, s, static_cast<const double*>(in), static_cast<double*>(out), total, lp, cp, tvn, nvn);
+    else hipLaunchKernelGGL(unpack_rows_kernel<float>, dim3(grid), dim3(256), 0, s, static_cast<const float*>(in), static_cast<float*>(out), total, lp, cp, tvn, nvn);
+  }
   return hipGetLastError();
 }
 

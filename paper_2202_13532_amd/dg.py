@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libdg.so")
 DG_OK, DG_ERR_INVALID, DG_ERR_UNSUPPORTED, DG_ERR_OOM, DG_ERR_DEVICE, DG_ERR_CFL, DG_ERR_NONFINITE = range(7)
 DG_F32, DG_F64 = 0, 1
 DG_VBC_PERIODIC, DG_VBC_ZERO_INFLOW = 0, 1
+DG_LAYOUT_DENSE, DG_LAYOUT_VPAD = 0, 1
 STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_INVALID", 2: "DG_ERR_UNSUPPORTED", 3: "DG_ERR_OOM",
                 4: "DG_ERR_DEVICE", 5: "DG_ERR_CFL", 6: "DG_ERR_NONFINITE"}
 
@@ -25,14 +26,15 @@ EXPORTED = ["dg_workspace_bytes", "dg_init", "dg_destroy", "dg_rhs", "dg_poisson
             "dg_nn_workspace_bytes", "dg_nn_init", "dg_nn_destroy", "dg_nn_param_count", "dg_nn_input_ld",
             "dg_nn_set_params", "dg_nn_get_params", "dg_nn_forward", "dg_nn_loss_grad", "dg_nn_adamw",
             "dg_projection_matrix", "dg_project", "dg_nn_features", "dg_nn_features_raw", "dg_nn_to_elements",
-            "dg_nn_column_stats", "dg_nn_rk_step", "dg_nn_last_error"]
+            "dg_nn_column_stats", "dg_nn_rk_step", "dg_nn_last_error", "dg_state_elems", "dg_state_pack",
+            "dg_state_unpack"]
 
 
 class dg_config(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int32), ("n", ctypes.c_int32), ("nelem", ctypes.c_int32 * 3),
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3), ("omega_c", ctypes.c_double),
                 ("pmax", ctypes.c_int32), ("storage", ctypes.c_int32), ("vbc", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("layout", ctypes.c_int32)]
 
 
 class dg_diag(ctypes.Structure):
@@ -107,6 +109,9 @@ def lib():
         "dg_nn_column_stats": (I, [P, P, ctypes.c_int64, I, dp, dp]),
         "dg_nn_rk_step": (I, [P, P, P, P, ctypes.c_float, P, D, I, diagp]),
         "dg_nn_last_error": (ctypes.c_char_p, [P]),
+        "dg_state_elems": (S, [P]),
+        "dg_state_pack": (I, [P, P, P]),
+        "dg_state_unpack": (I, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -130,7 +135,7 @@ def _dptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def make_config(nv, n, nelem, lo, hi, omega_c=0.0, pmax=0, storage="f32", vbc="periodic"):
+def make_config(nv, n, nelem, lo, hi, omega_c=0.0, pmax=0, storage="f32", vbc="periodic", layout="dense"):
     c = dg_config()
     c.nv, c.n = nv, n
     for a in range(3):
@@ -141,8 +146,18 @@ def make_config(nv, n, nelem, lo, hi, omega_c=0.0, pmax=0, storage="f32", vbc="p
     c.pmax = int(pmax)
     c.storage = DG_F64 if storage in ("f64", DG_F64) else DG_F32
     c.vbc = DG_VBC_ZERO_INFLOW if vbc in ("zero_inflow", DG_VBC_ZERO_INFLOW) else DG_VBC_PERIODIC
-    c.reserved = 0
+    c.layout = DG_LAYOUT_VPAD if layout in ("vpad", DG_LAYOUT_VPAD) else DG_LAYOUT_DENSE
     return c
+
+
+def state_shape(cfg):
+    """Tensor shape of a state of cfg's layout: [N0, n, N1, n, ...] dense, or
+    [Nx, n, Nu, n, 64 C] with padded v rows (C = ceil(Nv / floor(64 / n)))."""
+    ne = [cfg.nelem[a] for a in range(1 + cfg.nv)]
+    if cfg.layout == DG_LAYOUT_VPAD:
+        tv = 64 // cfg.n
+        return (ne[0], cfg.n, ne[1], cfg.n, 64 * ((ne[2] + tv - 1) // tv))
+    return tuple(x for N in ne for x in (N, cfg.n))
 
 
 # ---------------- C ABI, same names ----------------
@@ -204,6 +219,18 @@ def dg_last_error(ctx=None):
     return lib().dg_last_error(ctx).decode()
 
 
+def dg_state_elems(ctx):
+    return int(lib().dg_state_elems(ctx))
+
+
+def dg_state_pack(ctx, dense, state):
+    _check(lib().dg_state_pack(ctx, _ptr(dense), _ptr(state)), ctx)
+
+
+def dg_state_unpack(ctx, state, dense):
+    _check(lib().dg_state_unpack(ctx, _ptr(state), _ptr(dense)), ctx)
+
+
 def dg_basis(n):
     xi, w = np.zeros(n), np.zeros(n)
     ups, xf, dm = np.zeros(n * n), np.zeros(2 * n), np.zeros(n * n)
@@ -228,10 +255,10 @@ class Solver:
     """Owns a device workspace (torch uint8) and a library context."""
 
     def __init__(self, nv, n, nelem, lo, hi, omega_c=0.0, pmax=0, storage="f32", vbc="periodic",
-                 device="cuda"):
+                 device="cuda", layout="dense"):
         import torch
         self.torch = torch
-        self.cfg = make_config(nv, n, nelem, lo, hi, omega_c, pmax, storage, vbc)
+        self.cfg = make_config(nv, n, nelem, lo, hi, omega_c, pmax, storage, vbc, layout)
         nbytes = dg_workspace_bytes(self.cfg)
         if nbytes == 0:
             raise DGError(DG_ERR_INVALID, "invalid configuration")
@@ -243,7 +270,8 @@ class Solver:
         self.ctx = dg_init(self.cfg, self.ws, stream)
         self.nv, self.n = nv, n
         self.nelem = list(nelem[: 1 + nv])
-        self.shape = tuple(s for N in self.nelem for s in (N, n))
+        self.dense_shape = tuple(s for N in self.nelem for s in (N, n))
+        self.shape = state_shape(self.cfg)   # shape of this context's state arrays
         self.dtype = torch.float64 if storage in ("f64", DG_F64) else torch.float32
         self.pmax = pmax if pmax > 0 else nelem[0]
 
@@ -270,6 +298,22 @@ class Solver:
 
     def empty_state(self):
         return self.torch.empty(self.shape, dtype=self.dtype, device=self.device)
+
+    def pack(self, dense):
+        """Dense state (dense_shape) -> a state of this context's layout."""
+        t = self.torch
+        if dense.dtype != self.dtype or not dense.is_contiguous() or tuple(dense.shape) != self.dense_shape:
+            raise DGError(DG_ERR_INVALID, "dense state must be contiguous %s of shape %s" % (self.dtype, self.dense_shape))
+        out = self.empty_state()
+        dg_state_pack(self.ctx, dense, out)
+        return out
+
+    def unpack(self, f):
+        """State of this context's layout -> dense state (dense_shape)."""
+        self._check_state(f)
+        out = self.torch.empty(self.dense_shape, dtype=self.dtype, device=self.device)
+        dg_state_unpack(self.ctx, f, out)
+        return out
 
     def rhs(self, f, E=None, out=None):
         self._check_state(f)
@@ -365,10 +409,7 @@ class Batch:
         off = (-self.workspace.data_ptr()) % 256
         self.ws = self.workspace[off:off + nbytes]
         self.b = dg_batch_init(self.cfgs, self.ws, torch.cuda.current_stream(self.device).cuda_stream)
-        self.shapes = []
-        for c in self.cfgs:
-            ne = [c.nelem[a] for a in range(1 + c.nv)]
-            self.shapes.append(tuple(x for N in ne for x in (N, c.n)))
+        self.shapes = [state_shape(c) for c in self.cfgs]
 
     def close(self):
         if getattr(self, "b", None) is not None:

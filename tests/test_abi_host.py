@@ -81,6 +81,27 @@ def test_workspace_bytes_and_config_validation():
         assert dg.dg_workspace_bytes(c) == 0
 
 
+def test_padded_layout_validation_and_sizes():
+    _lib()
+    args = (2, 9, [64, 48, 48], [0, -6, -6], [4 * math.pi, 6, 6], 1.0)
+    dense = dg.make_config(*args)
+    vpad = dg.make_config(*args, layout="vpad")
+    dof = 64 * 48 * 48 * 9 ** 3
+    padded = 64 * 9 * 48 * 9 * 64 * 7          # 48 v elements in 7 chunks of 64 values
+    assert dg.state_shape(vpad) == (64, 9, 48, 9, 448)
+    assert dg.state_shape(dense) == (64, 9, 48, 9, 48, 9)
+    assert dg.dg_workspace_bytes(vpad) - dg.dg_workspace_bytes(dense) >= 2 * (padded - dof) * 4
+    # n = 8 with Nv a multiple of 8: the layouts coincide
+    c8 = dg.make_config(2, 8, [4, 4, 16], [0, -6, -6], [1, 6, 6], layout="vpad")
+    assert dg.state_shape(c8) == (4, 8, 4, 8, 128)
+    assert dg.dg_workspace_bytes(c8) == dg.dg_workspace_bytes(dg.make_config(2, 8, [4, 4, 16], [0, -6, -6], [1, 6, 6]))
+    # padded rows only for 1D2V; unknown layouts rejected
+    assert dg.dg_workspace_bytes(dg.make_config(1, 4, [4, 4], [0, -1], [1, 1], layout="vpad")) == 0
+    bad = dg.make_config(*args)
+    bad.layout = 2
+    assert dg.dg_workspace_bytes(bad) == 0
+
+
 def test_init_rejects_bad_arguments_before_touching_a_device():
     _lib()
     import ctypes

@@ -137,6 +137,31 @@ def test_one_step_parity(case, storage):
         assert _rel_l2(out, ref) < F32_REL_L2
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("vbc", ["zero_inflow", "periodic"])
+def test_steps_with_zero_speed_rows_match_oracle(vbc, storage):
+    # u elements [-6, 0] and [0, 6]: the u = 0 nodes give v-speed-zero rows
+    # inside tiles whose other rows all move one way (the idle-lane halo
+    # case), three steps from a rough random state
+    nv, n, nelem, lo, hi, wc = 2, 9, [3, 2, 7], [0.0, -6.0, -6.0], [6.0, 6.0, 6.0], 0.8
+    print("zero-speed rows", vbc, storage, flush=True)
+    s, g = _setup(nv, n, nelem, lo, hi, wc, storage, vbc)
+    f = inputs.random_nodal(g.shape, 1009)
+    fd = _dev(f, s)
+    fh = _host(fd)
+    dt = 0.5 * s.dt_max(float(s.poisson(fd).abs().max()))
+    recs = s.step(fd, dt, 3, diag=True)
+    assert all(r["finite"] == 1 for r in recs)
+    ops = lgl.operators(n)
+    for _ in range(3):
+        fh = rk.ssprk3_step(g, ops, fh, dt)
+    out = _host(fd)
+    if storage == "f64":
+        assert _rel_max(out, fh) < F64_REL_MAX * 10
+    else:
+        assert _rel_l2(out, fh) < F32_REL_L2
+
+
 def test_landau_history_fp64_matches_oracle_and_conserves_mass():
     """Landau damping (x 16, v 32 elements, n = 4, FP64): 200 steps, dt = 0.01."""
     nv, n, nelem, lo, hi, wc = _landau_1d1v()

@@ -15,6 +15,7 @@
 //   adamw_kernel, colstats_kernel: elementwise / reduction helpers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "nn_kernels.h"
@@ -195,89 +196,112 @@ __global__ void __launch_bounds__(kWave) gemm_bf16_kernel(GemmArgs g) {
 
 // ---------------------------------------------------------------------------
 // LDS-tiled BF16 MFMA GEMM for the network's shapes (rows = 4096 per coarse
-// state; inner and outer sizes 64..464).  A 256-thread work-group computes a
-// 64 x 64 tile of C, each wave a 32 x 32 quarter as 2 x 2 MFMA 16x16 tiles;
-// K advances 32 at a time through LDS, where both operands are stored with
-// k contiguous so that each lane fetches its 4 k values with one 8-byte LDS
-// read.  Global loads are 16 bytes (8 BF16) along the operand's contiguous
-// direction: A with k (AK) or m contiguous, B with n (BN) or k contiguous.
-// Split-K: work-group z covers k in [z Ks, (z+1) Ks); with more than one
-// slice, partial tiles go to `part` (slice-major, M x N each) and
-// gemm_reduce_kernel adds the slices in order (deterministic).
+// state, or several states per training step; inner and outer sizes
+// 64..464).  A 256-thread work-group computes a 64 x 64 tile of C, each wave
+// a 32 x 32 quarter as 2 x 2 tiles of v_mfma_f32_16x16x32_bf16 (FP32
+// accumulate).  Every global load of the work-group's k range (at most
+// kMaxKT tiles of 32) is issued before the first MFMA into registers, so
+// the load latency is paid once instead of once per k tile; the tiles then
+// pass through a double-buffered LDS stage (one barrier per tile), stored
+// with k contiguous so that each lane reads its 8 k values of a row or
+// column with one 16-byte LDS read.  Global loads are 16 bytes (8 BF16)
+// along the operand's contiguous direction: A with k (AK) or m contiguous,
+// B with n (BN) or k contiguous.  Split-K: work-group z covers k in
+// [z ks, (z+1) ks); with more than one slice, partial tiles go to `part`
+// (slice-major, M x N each) and gemm_reduce_kernel adds the slices in order
+// (deterministic).
+// MFMA lane layout (16x16x32): A row l mod 16, k = 8 floor(l/16) + t,
+// t = 0..7; B column l mod 16, same k; D column l mod 16, rows 4 floor(l/16)
+// + t, t = 0..3.
 // ---------------------------------------------------------------------------
-constexpr int kTM = 64, kTN = 64, kTK = 32, kTLd = kTK + 8;   // LDS row: 40 BF16
+constexpr int kTM = 64, kTN = 64, kTK = 32, kTLd = kTK + 8;   // LDS row: 40 BF16 (80 bytes)
+constexpr int kMaxKT = 16;                                   // k tiles held in registers (k range <= 512)
 
-__device__ __forceinline__ void load8(const uint16_t* base, size_t stride, int start, int bound, uint16_t* out) {
-  // 8 consecutive elements base[(start + i) * stride], zero beyond `bound`
-  if (stride == 1 && start + 8 <= bound) {
-    const uint4 v = *reinterpret_cast<const uint4*>(base + start);
-    out[0] = v.x & 0xffff; out[1] = v.x >> 16; out[2] = v.y & 0xffff; out[3] = v.y >> 16;
-    out[4] = v.z & 0xffff; out[5] = v.z >> 16; out[6] = v.w & 0xffff; out[7] = v.w >> 16;
-  } else {
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// 8 consecutive BF16 base[start .. start + 8), zero at and beyond `bound`
+// (base + start is 16-byte aligned when the 8 values are all in range)
+__device__ __forceinline__ uint4 load8v(const uint16_t* base, int start, int bound) {
+  if (start + 8 <= bound) return *reinterpret_cast<const uint4*>(base + start);
+  uint16_t v[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) out[i] = start + i < bound ? base[static_cast<size_t>(start + i) * stride] : uint16_t(0);
+  for (int i = 0; i < 8; ++i) v[i] = start + i < bound ? base[start + i] : uint16_t(0);
+  return uint4{v[0] | (uint32_t(v[1]) << 16), v[2] | (uint32_t(v[3]) << 16), v[4] | (uint32_t(v[5]) << 16),
+               v[6] | (uint32_t(v[7]) << 16)};
+}
+
+// 8 values of one uint4 to LDS entries tile[(c + i) * kTLd + kk] (a transpose)
+__device__ __forceinline__ void scatter8(uint16_t* tile, int c, int kk, uint4 v) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    tile[(c + 2 * i) * kTLd + kk] = static_cast<uint16_t>(w[i] & 0xffffu);
+    tile[(c + 2 * i + 1) * kTLd + kk] = static_cast<uint16_t>(w[i] >> 16);
   }
 }
 
 template <bool AK, bool BN>
 __global__ void __launch_bounds__(256) gemm_bf16_tiled_kernel(GemmArgs g, float* part, int ks) {
-  __shared__ uint16_t As[kTM * kTLd];
-  __shared__ uint16_t Bs[kTN * kTLd];
+  __shared__ uint16_t As[2][kTM * kTLd];
+  __shared__ uint16_t Bs[2][kTN * kTLd];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * kTM, n0 = blockIdx.y * kTN;
   const int kb = blockIdx.z * ks, ke = min(g.K, kb + ks);
+  const int nt = (ke - kb + kTK - 1) / kTK;   // <= kMaxKT (launch_gemm_tiled bounds ks)
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  // load roles: (row r, k chunk 8 q) for operands stored with k contiguous,
+  // (k row kk, chunk of 8 along m or n) for the others
+  const int r4 = tid >> 2, q4 = (tid & 3) * 8, kk8 = tid >> 3, c8 = (tid & 7) * 8;
+  uint4 ra[kMaxKT], rb[kMaxKT];
+#pragma unroll
+  for (int t = 0; t < kMaxKT; ++t) {
+    if (t < nt) {
+      const int k0 = kb + t * kTK;
+      if (AK) {
+        const int m = m0 + r4;
+        ra[t] = m < g.M ? load8v(g.A + static_cast<size_t>(m) * g.sam, k0 + q4, ke) : uint4{0, 0, 0, 0};
+      } else {
+        const int k = k0 + kk8;
+        ra[t] = k < ke ? load8v(g.A + static_cast<size_t>(k) * g.sak, m0 + c8, g.M) : uint4{0, 0, 0, 0};
+      }
+      if (BN) {
+        const int k = k0 + kk8;
+        rb[t] = k < ke ? load8v(g.B + static_cast<size_t>(k) * g.sbk, n0 + c8, g.N) : uint4{0, 0, 0, 0};
+      } else {
+        const int n = n0 + r4;
+        rb[t] = n < g.N ? load8v(g.B + static_cast<size_t>(n) * g.sbn, k0 + q4, ke) : uint4{0, 0, 0, 0};
+      }
+    }
+  }
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k0 = kb; k0 < ke; k0 += kTK) {
-    uint16_t v[8];
-    if (AK) {   // thread: row r, k chunk c (8 values along k)
-      const int r = tid >> 2, c = (tid & 3) * 8, m = m0 + r;
-      if (m < g.M) load8(g.A + static_cast<size_t>(m) * g.sam, 1, k0 + c, ke, v);
-      else for (int i = 0; i < 8; ++i) v[i] = 0;
-      *reinterpret_cast<uint4*>(&As[r * kTLd + c]) =
-          uint4{v[0] | (uint32_t(v[1]) << 16), v[2] | (uint32_t(v[3]) << 16), v[4] | (uint32_t(v[5]) << 16),
-                v[6] | (uint32_t(v[7]) << 16)};
-    } else {    // thread: k row kk, m chunk c (8 values along m)
-      const int kk = tid >> 3, c = (tid & 7) * 8, k = k0 + kk;
-      if (k < ke) load8(g.A + static_cast<size_t>(k) * g.sak, 1, m0 + c, g.M, v);
-      else for (int i = 0; i < 8; ++i) v[i] = 0;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) As[(c + i) * kTLd + kk] = v[i];
-    }
-    if (BN) {   // thread: k row kk, n chunk c
-      const int kk = tid >> 3, c = (tid & 7) * 8, k = k0 + kk;
-      if (k < ke) load8(g.B + static_cast<size_t>(k) * g.sbk, 1, n0 + c, g.N, v);
-      else for (int i = 0; i < 8; ++i) v[i] = 0;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) Bs[(c + i) * kTLd + kk] = v[i];
-    } else {    // thread: column r, k chunk c
-      const int r = tid >> 2, c = (tid & 3) * 8, n = n0 + r;
-      if (n < g.N) load8(g.B + static_cast<size_t>(n) * g.sbn, 1, k0 + c, ke, v);
-      else for (int i = 0; i < 8; ++i) v[i] = 0;
-      *reinterpret_cast<uint4*>(&Bs[r * kTLd + c]) =
-          uint4{v[0] | (uint32_t(v[1]) << 16), v[2] | (uint32_t(v[3]) << 16), v[4] | (uint32_t(v[5]) << 16),
-                v[6] | (uint32_t(v[7]) << 16)};
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < kTK; kk += 16) {
-      const int kq = kk + 4 * (lane >> 4);
-      bf16x4 af[2], bf[2];
+  for (int t = 0; t < kMaxKT; ++t) {
+    if (t < nt) {   // uniform over the work-group
+      // buffer t & 1 was last read in tile t - 2, before every thread passed
+      // the barrier of tile t - 1
+      uint16_t* as = As[t & 1];
+      uint16_t* bs = Bs[t & 1];
+      if (AK) *reinterpret_cast<uint4*>(&as[r4 * kTLd + q4]) = ra[t];
+      else scatter8(as, c8, kk8, ra[t]);
+      if (BN) scatter8(bs, c8, kk8, rb[t]);
+      else *reinterpret_cast<uint4*>(&bs[r4 * kTLd + q4]) = rb[t];
+      __syncthreads();
+      const int kq = 8 * (lane >> 4);
+      bf16x8 af[2], bf[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        af[i] = *reinterpret_cast<const bf16x4*>(&As[(wm + 16 * i + (lane & 15)) * kTLd + kq]);
-        bf[i] = *reinterpret_cast<const bf16x4*>(&Bs[(wn + 16 * i + (lane & 15)) * kTLd + kq]);
+        af[i] = *reinterpret_cast<const bf16x8*>(&as[(wm + 16 * i + (lane & 15)) * kTLd + kq]);
+        bf[i] = *reinterpret_cast<const bf16x8*>(&bs[(wn + 16 * i + (lane & 15)) * kTLd + kq]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
   }
   // D layout: column lane % 16, rows 4 (lane / 16) + t
 #pragma unroll
@@ -594,9 +618,15 @@ hipError_t launch_gemm_tiled(const GemmArgs& g, float* part, size_t part_floats,
   // work-groups per CU, keeping slices of >= 256 so the reduction stays short
   int slices = 1;
   while (tiles * slices < 2 * cus && g.K / (2 * slices) >= 256) slices *= 2;
-  while (slices > 1 && static_cast<size_t>(slices) * g.M * g.N > part_floats) slices /= 2;
+  // each slice's k range must fit the kernel's register stage
+  int smin = 1;
+  while (static_cast<long long>(smin) * kMaxKT * kTK < g.K) smin *= 2;
+  slices = std::max(slices, smin);
+  while (slices > smin && static_cast<size_t>(slices) * g.M * g.N > part_floats) slices /= 2;
+  if (slices > 1 && static_cast<size_t>(slices) * g.M * g.N > part_floats) return launch_gemm(g, s);
   const int ks = ((g.K + slices - 1) / slices + kTK - 1) / kTK * kTK;
   slices = (g.K + ks - 1) / ks;
+  if (ks > kMaxKT * kTK) return hipErrorInvalidValue;
   float* p = slices > 1 ? part : nullptr;
   const dim3 grid((g.M + kTM - 1) / kTM, (g.N + kTN - 1) / kTN, slices);
   if (ak && bn) hipLaunchKernelGGL((gemm_bf16_tiled_kernel<true, true>), grid, dim3(256), 0, s, g, p, ks);

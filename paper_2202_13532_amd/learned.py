@@ -56,6 +56,7 @@ class Config:
     snapshot_stride: int = 220         # fine steps between snapshots (64 x 220 spans t = 0..9)
     spinup_steps: int = 0              # fine steps before the first snapshot
     epochs: int = 5
+    snapshots_per_step: int = 1        # minibatch = this many whole snapshots (ne rows each)
     lr: float = 1e-3
     weight_decay: float = 1e-4
     init_seed: int = 12345
@@ -88,7 +89,7 @@ class LearnedCorrection:
         self.nfeat = (8 if c.fluct else 7) * self.nb + n
         self.ne = c.nelem_coarse ** 3
         self.sizes = [self.nfeat] + list(c.hidden) + [self.nb]
-        self.net = dg.Network(self.sizes, self.ne)
+        self.net = dg.Network(self.sizes, self.ne * max(1, c.snapshots_per_step))
         self.device = self.fine.device
         self.mean = None
         self.inv_std = None
@@ -217,15 +218,31 @@ class LearnedCorrection:
         epochs = c.epochs if epochs is None else epochs
         lr0 = c.lr if lr is None else lr
         ns = X.shape[0]
-        total = epochs * ns
+        k = max(1, min(c.snapshots_per_step, ns))
         rng = np.random.default_rng(seed)
+        if k > 1:
+            # one shuffled copy (device-to-device copies), then groups of k
+            # consecutive snapshots form the minibatches, visited in a new
+            # random order every epoch
+            Xs, Ts = self.torch.empty_like(X), self.torch.empty_like(T)
+            for j, i in enumerate(rng.permutation(ns)):
+                Xs[j].copy_(X[i])
+                Ts[j].copy_(T[i])
+            X = Xs.reshape(ns * self.ne, -1)
+            T = Ts.reshape(ns * self.ne, -1)
+        ngroups = ns // k
+        rows = k * self.ne
+        total = epochs * ngroups
         history = []
         step = 0
         for ep in range(epochs):
-            for i in rng.permutation(ns):
+            for i in rng.permutation(ngroups):
                 lr_t = 0.5 * lr0 * (1.0 + math.cos(math.pi * step / max(total, 1)))
                 want = (step % log_every == 0) or step == total - 1
-                loss, _ = self.net.loss_grad(X[i], T[i], want_loss=want)
+                if k > 1:
+                    loss, _ = self.net.loss_grad(X[i * rows:(i + 1) * rows], T[i * rows:(i + 1) * rows], want_loss=want)
+                else:
+                    loss, _ = self.net.loss_grad(X[i], T[i], want_loss=want)
                 self.net.adamw(lr_t, c.weight_decay)
                 if want:
                     history.append((step, loss))

@@ -34,7 +34,7 @@ struct NNLayout {
   std::vector<size_t> offW, offb;     // element offsets into the parameter vector
   size_t nparam = 0;
   size_t off_P, off_Pbf, off_G, off_m, off_v, off_Ytmp, off_dA, off_dZ, off_dZb, off_loss, off_sum, off_sumsq,
-      off_Xf, off_Yo, off_corr, off_xm1, off_xm2, off_gpart, total;
+      off_Xf, off_Yo, off_corr, off_xm1, off_xm2, off_gpart, off_cpart, total;
   size_t gpart_floats = 0;   // split-K scratch of the GEMMs
   std::vector<size_t> off_A, off_Z;   // A[l]: BF16 input of layer l (l >= 1); Z[l]: pre-activation of layer l
 };
@@ -93,6 +93,7 @@ NNLayout nn_layout(const int32_t* sizes, int32_t nlayers, int32_t max_rows) {
   for (int l = 0; l < nlayers; ++l) wmm = std::max(wmm, static_cast<size_t>(sizes[l]) * sizes[l + 1]);
   N.gpart_floats = std::max(4 * R * static_cast<size_t>(N.wmax), 32 * wmm);
   N.off_gpart = take(N.gpart_floats * 4);
+  N.off_cpart = take(static_cast<size_t>(dgn::kColsumPart) * N.wmax * 4);
   N.total = o;
   return N;
 }
@@ -239,19 +240,18 @@ dg_status forward_on(dg_nn* nn, const uint16_t* X, int rows, float* Y, bool keep
   for (int l = 0; l < N.L; ++l) {
     const int in = N.sizes[l], out = N.sizes[l + 1];
     const bool last = l == N.L - 1;
-    float* Yt = nn->at<float>(N.off_Ytmp);
-    NN_HIP(nn, run_gemm(nn, gemm(A, N.ld[l], 1, nn->at<uint16_t>(N.off_Pbf) + N.offW[l], out, 1, Yt, out, rows, out, in), s));
-    dgn::BiasActArgs b{};
-    b.Y = Yt;
-    b.bias = nn->at<float>(N.off_P) + N.offb[l];
-    b.Z = (!last && keep) ? nn->at<float>(N.off_Z[l]) : nullptr;
-    b.Af = last ? Y : nullptr;
-    b.Abf = last ? nullptr : nn->at<uint16_t>(N.off_A[l + 1]);
-    b.rows = rows;
-    b.cols = out;
-    b.ld = N.ld[l + 1];
-    b.gelu = last ? 0 : 1;
-    NN_HIP(nn, dgn::launch_bias_act(b, s));
+    // bias, GELU and the BF16 copy for the next layer in the GEMM's epilogue
+    // (the activation buffers' padding columns are zero from initialisation
+    // and never written)
+    dgn::GemmArgs g = gemm(A, N.ld[l], 1, nn->at<uint16_t>(N.off_Pbf) + N.offW[l], out, 1, nullptr, out, rows, out, in);
+    g.epi = 1;
+    g.gelu = last ? 0 : 1;
+    g.bias = nn->at<float>(N.off_P) + N.offb[l];
+    g.Z = (!last && keep) ? nn->at<float>(N.off_Z[l]) : nullptr;
+    g.Af = last ? Y : nullptr;
+    g.Abf = last ? nullptr : nn->at<uint16_t>(N.off_A[l + 1]);
+    g.lda = N.ld[l + 1];
+    NN_HIP(nn, run_gemm(nn, g, s));
     if (!last) A = nn->at<uint16_t>(N.off_A[l + 1]);
   }
   return DG_OK;
@@ -426,7 +426,7 @@ dg_status dg_nn_loss_grad(dg_nn* nn, const uint16_t* X, const float* T, int32_t 
   for (int l = N.L - 1; l >= 0; --l) {
     const int in = N.sizes[l], out = N.sizes[l + 1];
     const uint16_t* A = l == 0 ? X : nn->at<uint16_t>(N.off_A[l]);
-    NN_HIP(nn, dgn::launch_colsum(dZ, rows, out, G + N.offb[l], s));
+    NN_HIP(nn, dgn::launch_colsum(dZ, rows, out, G + N.offb[l], nn->at<float>(N.off_cpart), s));
     // dW = A^T dZ  (in x out, K = rows)
     NN_HIP(nn, run_gemm(nn, gemm(A, 1, N.ld[l], dZb, N.ld[l + 1], 1, G + N.offW[l], out, in, out, rows), s));
     if (l > 0) {

@@ -40,15 +40,14 @@ struct GemmArgs {
   size_t sam, sak, sbk, sbn, scm, scn;
   int M, N, K;
   float beta;
-};
-
-struct BiasActArgs {
-  const float* Y;       // rows x cols
-  const float* bias;    // cols or nullptr
-  float* Z;             // rows x cols pre-activation (or nullptr)
-  float* Af;            // rows x cols activation FP32 (or nullptr)
-  uint16_t* Abf;        // rows x ld activation BF16 (or nullptr)
-  int rows, cols, ld, gelu;
+  // Fused layer epilogue instead of storing C (when epi != 0):
+  //   z = acc + bias[n];  Z[m*N + n] = z;  v = gelu ? GELU(z) : z;
+  //   Af[m*N + n] = v;  Abf[m*lda + n] = BF16(v)   (each output optional)
+  int epi, gelu, lda;
+  const float* bias;
+  float* Z;
+  float* Af;
+  uint16_t* Abf;
 };
 
 struct AdamArgs {
@@ -72,11 +71,12 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
 // has no unit stride or is not 16-byte aligned).  `part`: device scratch of
 // part_floats floats for the split-K slices; `cus`: compute units.
 hipError_t launch_gemm_tiled(const GemmArgs& g, float* part, size_t part_floats, int cus, hipStream_t s);
-hipError_t launch_bias_act(const BiasActArgs& a, hipStream_t s);
 hipError_t launch_gelu_back(const float* dA, const float* Z, float* dZ, uint16_t* dZb, int rows, int cols, int ld, hipStream_t s);
 hipError_t launch_mse(const float* Y, const float* T, int rows, int cols, int ld, float inv_count, float* dY, uint16_t* dYb,
                       double* partial, int nblocks, hipStream_t s);
-hipError_t launch_colsum(const float* in, int rows, int cols, float* out, hipStream_t s);
+// column sums (bias gradients); part: 32 x cols floats of scratch
+constexpr int kColsumPart = 32;
+hipError_t launch_colsum(const float* in, int rows, int cols, float* out, float* part, hipStream_t s);
 hipError_t launch_adamw(const AdamArgs& a, hipStream_t s);
 hipError_t launch_colstats(const float* X, size_t rows, int ld, int cols, double* sum, double* sumsq, hipStream_t s);
 // out = scale * (in - sub - xm) element-major (sub, xm optional; xm per (u, v) node)

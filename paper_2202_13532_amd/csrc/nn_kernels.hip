@@ -8,10 +8,15 @@
 //                        and converted to BF16 (one row per element).
 //   scatter_kernel       network output (element-major) -> state layout, with
 //                        the element's weighted mean removed (mass neutral).
-//   gemm_bf16_kernel     C = A B with v_mfma_f32_16x16x16_bf16: one wave per
-//                        16x16 tile of C; A and B addressed by strides so the
-//                        same kernel serves X W, dY W^T and X^T dY.
-//   bias_act_kernel, gelu_back_kernel, mse_kernel, colsum_kernel,
+//   gemm_bf16_tiled_kernel  C = A B with v_mfma_f32_16x16x32_bf16, a 64x64
+//                        tile of C per work-group, split K with an ordered
+//                        reduction (gemm_reduce_kernel); the same kernel
+//                        serves X W, dY W^T and X^T dY, and the forward
+//                        layers take bias + GELU + BF16 conversion in its
+//                        epilogue.
+//   gemm_bf16_kernel     fallback for operands without a unit stride: one
+//                        wave per 16x16 tile with v_mfma_f32_16x16x16_bf16.
+//   gelu_back_kernel, mse_kernel, colsum_kernel,
 //   adamw_kernel, colstats_kernel: elementwise / reduction helpers.
 #include <hip/hip_runtime.h>
 
@@ -36,6 +41,20 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __builtin_bit_cast(fl
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+// Final value of C(m, n): a plain store, or the fused layer epilogue.
+__device__ __forceinline__ void gemm_store(const GemmArgs& g, int m, int n, float acc) {
+  if (!g.epi) {
+    g.C[static_cast<size_t>(m) * g.scm + static_cast<size_t>(n) * g.scn] = acc;
+    return;
+  }
+  const float z = acc + (g.bias ? g.bias[n] : 0.0f);
+  const size_t zi = static_cast<size_t>(m) * g.N + n;
+  if (g.Z) g.Z[zi] = z;
+  const float v = g.gelu ? gelu(z) : z;
+  if (g.Af) g.Af[zi] = v;
+  if (g.Abf) g.Abf[static_cast<size_t>(m) * g.lda + n] = f2bf(v);
 }
 
 // ---------------------------------------------------------------------------
@@ -82,18 +101,20 @@ __global__ void f64_to_f32_kernel(const double* in, float* out, size_t n) {
 // then the x-1, x+1, u-1, u+1, v-1, v+1 neighbour blocks (periodic), then E at
 // the element's n x nodes, then zero padding up to ld.  Column c is
 // normalised as (value - mean[c]) * inv_std[c] before conversion to BF16.
-// One thread per (row, column).
+// One thread per (row, column); 32-bit index arithmetic (launch_gather checks
+// that rows x ld and the state size fit).
 // ---------------------------------------------------------------------------
 __global__ void gather_kernel(GatherArgs a) {
   const int n = a.n, nb = n * n * n;
-  const size_t total = static_cast<size_t>(a.Nx) * a.Nu * a.Nv * a.ld;
-  const size_t tid = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const unsigned total = static_cast<unsigned>(a.Nx) * a.Nu * a.Nv * a.ld;
+  const unsigned tid = blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= total) return;
-  const int col = static_cast<int>(tid % a.ld);
-  const size_t e = tid / a.ld;
-  const int iv = static_cast<int>(e % a.Nv);
-  const int iu = static_cast<int>((e / a.Nv) % a.Nu);
-  const int ix = static_cast<int>(e / (static_cast<size_t>(a.Nv) * a.Nu));
+  const int col = static_cast<int>(tid % static_cast<unsigned>(a.ld));
+  const unsigned e = tid / static_cast<unsigned>(a.ld);
+  const int iv = static_cast<int>(e % static_cast<unsigned>(a.Nv));
+  const unsigned e2 = e / static_cast<unsigned>(a.Nv);
+  const int iu = static_cast<int>(e2 % static_cast<unsigned>(a.Nu));
+  const int ix = static_cast<int>(e2 / static_cast<unsigned>(a.Nu));
   float val = 0.0f;
   if (col < 7 * nb) {
     const int blk = col / nb, loc = col % nb;
@@ -108,15 +129,15 @@ __global__ void gather_kernel(GatherArgs a) {
       default: break;
     }
     const int jx = loc / (n * n), ju = (loc / n) % n, jv = loc % n;
-    const size_t q = ((static_cast<size_t>(eu) * n + ju) * a.Nv + ev) * n + jv;
-    const size_t idx = (static_cast<size_t>(ex) * n + jx) * (static_cast<size_t>(a.Nu) * n * a.Nv * n) + q;
+    const unsigned q = ((static_cast<unsigned>(eu) * n + ju) * a.Nv + ev) * n + jv;
+    const unsigned idx = (static_cast<unsigned>(ex) * n + jx) * (static_cast<unsigned>(a.Nu) * n * a.Nv * n) + q;
     val = a.xmean ? a.f[idx] - a.xmean[q] : a.f[idx];
   } else if (col < 7 * nb + n) {
     val = static_cast<float>(a.E[ix * n + (col - 7 * nb)]);
   } else if (a.xmean && col < 8 * nb + n) {
     const int loc = col - 7 * nb - n;
     const int ju = (loc / n) % n, jv = loc % n;
-    val = a.xmean[((static_cast<size_t>(iu) * n + ju) * a.Nv + iv) * n + jv];
+    val = a.xmean[((static_cast<unsigned>(iu) * n + ju) * a.Nv + iv) * n + jv];
   }
   const bool real = col < a.nfeat;
   const float z = real ? (val - a.mean[col]) * a.inv_std[col] : 0.0f;
@@ -125,31 +146,36 @@ __global__ void gather_kernel(GatherArgs a) {
 
 // Network output Y[e][loc] (loc = (jx*n + ju)*n + jv), scaled by `scale`,
 // minus its element mean under the product LGL weights w_jx w_ju w_jv, written
-// to the state layout (FP32).  One thread per element.
-__global__ void scatter_kernel(ScatterArgs a) {
-  const int n = a.n;
-  const size_t ne = static_cast<size_t>(a.Nx) * a.Nu * a.Nv;
-  const size_t e = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
-  const int iv = static_cast<int>(e % a.Nv);
-  const int iu = static_cast<int>((e / a.Nv) % a.Nu);
-  const int ix = static_cast<int>(e / (static_cast<size_t>(a.Nv) * a.Nu));
-  const float* y = a.Y + e * a.ldy;
-  double num = 0.0, den = 0.0;   // FP64: the removed mean must not carry a rounding bias
-  for (int jx = 0; jx < n; ++jx)
-    for (int ju = 0; ju < n; ++ju)
-      for (int jv = 0; jv < n; ++jv) {
-        const double w = static_cast<double>(a.w[jx]) * a.w[ju] * a.w[jv];
-        num += w * y[(jx * n + ju) * n + jv];
-        den += w;
-      }
-  const float mean = a.mass_neutral ? static_cast<float>(num / den) : 0.0f;
-  for (int jx = 0; jx < n; ++jx)
-    for (int ju = 0; ju < n; ++ju)
-      for (int jv = 0; jv < n; ++jv) {
-        const size_t idx = ((((static_cast<size_t>(ix) * n + jx) * a.Nu + iu) * n + ju) * a.Nv + iv) * n + jv;
-        a.out[idx] = a.scale * (y[(jx * n + ju) * n + jv] - mean);
-      }
+// to the state layout (FP32).  One 64-lane wave per element: the lanes stride
+// over the n^3 nodes, the weighted sum is formed in FP64 and combined by a
+// fixed butterfly (reproducible), and the outputs are written by node.
+__global__ void __launch_bounds__(kWave) scatter_kernel(ScatterArgs a) {
+  const int n = a.n, nn = n * n, nb = nn * n;
+  const unsigned e = blockIdx.x;   // element, v fastest
+  const int lane = threadIdx.x;
+  const int iv = static_cast<int>(e % static_cast<unsigned>(a.Nv));
+  const unsigned e2 = e / static_cast<unsigned>(a.Nv);
+  const int iu = static_cast<int>(e2 % static_cast<unsigned>(a.Nu));
+  const int ix = static_cast<int>(e2 / static_cast<unsigned>(a.Nu));
+  const float* y = a.Y + static_cast<size_t>(e) * a.ldy;
+  float mean = 0.0f;
+  if (a.mass_neutral) {
+    double num = 0.0;   // FP64: the removed mean must not carry a rounding bias
+    for (int i = lane; i < nb; i += kWave) {
+      const int jx = i / nn, ju = (i / n) % n, jv = i % n;
+      num += static_cast<double>(a.w[jx]) * a.w[ju] * a.w[jv] * y[i];
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) num += __shfl_xor(num, off);
+    double sw = 0.0;
+    for (int j = 0; j < n; ++j) sw += a.w[j];
+    mean = static_cast<float>(num / (sw * sw * sw));
+  }
+  for (int i = lane; i < nb; i += kWave) {
+    const int jx = i / nn, ju = (i / n) % n, jv = i % n;
+    const size_t idx = ((((static_cast<size_t>(ix) * n + jx) * a.Nu + iu) * n + ju) * a.Nv + iv) * n + jv;
+    a.out[idx] = a.scale * (y[i] - mean);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -188,8 +214,12 @@ __global__ void __launch_bounds__(kWave) gemm_bf16_kernel(GemmArgs g) {
   for (int t = 0; t < 4; ++t) {
     const int cm = m0 + kb + t;
     if (cm < g.M && cn < g.N) {
-      float* c = g.C + static_cast<size_t>(cm) * g.scm + static_cast<size_t>(cn) * g.scn;
-      *c = g.beta != 0.0f ? acc[t] + g.beta * *c : acc[t];
+      if (g.epi) {
+        gemm_store(g, cm, cn, acc[t]);
+      } else {
+        float* c = g.C + static_cast<size_t>(cm) * g.scm + static_cast<size_t>(cn) * g.scn;
+        *c = g.beta != 0.0f ? acc[t] + g.beta * *c : acc[t];
+      }
     }
   }
 }
@@ -199,7 +229,8 @@ __global__ void __launch_bounds__(kWave) gemm_bf16_kernel(GemmArgs g) {
 // state, or several states per training step; inner and outer sizes
 // 64..464).  A 256-thread work-group computes a 64 x 64 tile of C, each wave
 // a 32 x 32 quarter as 2 x 2 tiles of v_mfma_f32_16x16x32_bf16 (FP32
-// accumulate).  Every global load of the work-group's k range (at most
+// accumulate); when 64-row tiles would leave CUs idle, 32-row tiles (each
+// wave 16 x 32) double the work-groups.  Every global load of the work-group's k range (at most
 // kMaxKT tiles of 32) is issued before the first MFMA into registers, so
 // the load latency is paid once instead of once per k tile; the tiles then
 // pass through a double-buffered LDS stage (one barrier per tile), stored
@@ -240,24 +271,29 @@ __device__ __forceinline__ void scatter8(uint16_t* tile, int c, int kk, uint4 v)
   }
 }
 
-template <bool AK, bool BN>
+template <bool AK, bool BN, int TM>
 __global__ void __launch_bounds__(256) gemm_bf16_tiled_kernel(GemmArgs g, float* part, int ks) {
-  __shared__ uint16_t As[2][kTM * kTLd];
+  constexpr int MI = TM / 32;   // 16-row MFMA tiles per wave along m
+  __shared__ uint16_t As[2][TM * kTLd];
   __shared__ uint16_t Bs[2][kTN * kTLd];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.x * kTM, n0 = blockIdx.y * kTN;
+  const int m0 = blockIdx.x * TM, n0 = blockIdx.y * kTN;
   const int kb = blockIdx.z * ks, ke = min(g.K, kb + ks);
   const int nt = (ke - kb + kTK - 1) / kTK;   // <= kMaxKT (launch_gemm_tiled bounds ks)
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * 32;
   // load roles: (row r, k chunk 8 q) for operands stored with k contiguous,
-  // (k row kk, chunk of 8 along m or n) for the others
+  // (k row kk, chunk of 8 along m or n) for the others; with TM = 32 half of
+  // the threads have no A role
   const int r4 = tid >> 2, q4 = (tid & 3) * 8, kk8 = tid >> 3, c8 = (tid & 7) * 8;
+  const bool arole = AK ? r4 < TM : c8 < TM;
   uint4 ra[kMaxKT], rb[kMaxKT];
 #pragma unroll
   for (int t = 0; t < kMaxKT; ++t) {
     if (t < nt) {
       const int k0 = kb + t * kTK;
-      if (AK) {
+      if (!arole) {
+        ra[t] = uint4{0, 0, 0, 0};
+      } else if (AK) {
         const int m = m0 + r4;
         ra[t] = m < g.M ? load8v(g.A + static_cast<size_t>(m) * g.sam, k0 + q4, ke) : uint4{0, 0, 0, 0};
       } else {
@@ -273,9 +309,9 @@ __global__ void __launch_bounds__(256) gemm_bf16_tiled_kernel(GemmArgs g, float*
       }
     }
   }
-  f32x4 acc[2][2];
+  f32x4 acc[MI][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -285,27 +321,28 @@ __global__ void __launch_bounds__(256) gemm_bf16_tiled_kernel(GemmArgs g, float*
       // the barrier of tile t - 1
       uint16_t* as = As[t & 1];
       uint16_t* bs = Bs[t & 1];
-      if (AK) *reinterpret_cast<uint4*>(&as[r4 * kTLd + q4]) = ra[t];
-      else scatter8(as, c8, kk8, ra[t]);
+      if (arole) {
+        if (AK) *reinterpret_cast<uint4*>(&as[r4 * kTLd + q4]) = ra[t];
+        else scatter8(as, c8, kk8, ra[t]);
+      }
       if (BN) scatter8(bs, c8, kk8, rb[t]);
       else *reinterpret_cast<uint4*>(&bs[r4 * kTLd + q4]) = rb[t];
       __syncthreads();
       const int kq = 8 * (lane >> 4);
-      bf16x8 af[2], bf[2];
+      bf16x8 af[MI], bf[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        af[i] = *reinterpret_cast<const bf16x8*>(&as[(wm + 16 * i + (lane & 15)) * kTLd + kq]);
-        bf[i] = *reinterpret_cast<const bf16x8*>(&bs[(wn + 16 * i + (lane & 15)) * kTLd + kq]);
-      }
+      for (int i = 0; i < MI; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&as[(wm + 16 * i + (lane & 15)) * kTLd + kq]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i) bf[i] = *reinterpret_cast<const bf16x8*>(&bs[(wn + 16 * i + (lane & 15)) * kTLd + kq]);
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
   }
   // D layout: column lane % 16, rows 4 (lane / 16) + t
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int n = n0 + wn + 16 * j + (lane & 15);
@@ -314,7 +351,7 @@ __global__ void __launch_bounds__(256) gemm_bf16_tiled_kernel(GemmArgs g, float*
         const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + t;
         if (m < g.M && n < g.N) {
           if (part) part[(static_cast<size_t>(blockIdx.z) * g.M + m) * g.N + n] = acc[i][j][t];
-          else g.C[static_cast<size_t>(m) * g.scm + static_cast<size_t>(n) * g.scn] = acc[i][j][t];
+          else gemm_store(g, m, n, acc[i][j][t]);
         }
       }
     }
@@ -328,28 +365,7 @@ __global__ void gemm_reduce_kernel(const float* part, int slices, GemmArgs g) {
   float s = 0.0f;
 #pragma unroll 8
   for (int z = 0; z < slices; ++z) s += part[z * mn + i];
-  const size_t m = i / g.N, n = i % g.N;
-  g.C[m * g.scm + n * g.scn] = s;
-}
-
-// Z = Y + bias (per column), stored FP32; A = act(Z) stored BF16 (ld columns,
-// padding columns set to zero) and optionally FP32.
-__global__ void bias_act_kernel(BiasActArgs a) {
-  const size_t total = static_cast<size_t>(a.rows) * a.ld;
-  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int col = static_cast<int>(i % a.ld);
-  const size_t row = i / a.ld;
-  if (col >= a.cols) {
-    if (a.Abf) a.Abf[i] = 0;
-    return;
-  }
-  const size_t zi = row * a.cols + col;
-  const float z = a.Y[zi] + (a.bias ? a.bias[col] : 0.0f);
-  if (a.Z) a.Z[zi] = z;
-  const float v = a.gelu ? gelu(z) : z;
-  if (a.Af) a.Af[zi] = v;
-  if (a.Abf) a.Abf[i] = f2bf(v);
+  gemm_store(g, static_cast<int>(i / g.N), static_cast<int>(i % g.N), s);
 }
 
 // dZ = dA * gelu'(Z) (FP32), and its BF16 copy with ld columns.
@@ -394,20 +410,39 @@ __global__ void mse_kernel(const float* Y, const float* T, int rows, int cols, i
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// Column sums (bias gradients): out[c] = sum_rows in[row*cols + c]; one block
-// per column, fixed-order tree.
-__global__ void colsum_kernel(const float* in, int rows, int cols, float* out) {
+// Column sums of a rows x cols FP32 matrix in two fixed-order passes:
+// colsum_part_kernel: work-group (column block of 64, row slice z) -> each
+// thread sums every 4th row of the slice for one column (coalesced 256-byte
+// rows), the four row groups are added in order -> part[z][col];
+// colsum_final_kernel: out[col] = sum over the slices in order.
+__global__ void __launch_bounds__(256) colsum_part_kernel(const float* in, int rows, int cols, int per, float* part) {
   __shared__ float red[256];
-  const int c = blockIdx.x;
-  float s = 0.0f;
-  for (int r = threadIdx.x; r < rows; r += blockDim.x) s += in[static_cast<size_t>(r) * cols + c];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * per, r1 = min(rows, r0 + per);
+  float acc = 0.0f;
+  // unrolled so that the loads are in flight together (the sum order is fixed)
+  if (c < cols) {
+#pragma unroll 16
+    for (int r = r0 + g; r < r1; r += 4) acc += in[static_cast<size_t>(r) * cols + c];
   }
-  if (threadIdx.x == 0) out[c] = red[0];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (g == 0 && c < cols)
+    part[static_cast<size_t>(blockIdx.y) * cols + c] =
+        ((red[threadIdx.x] + red[threadIdx.x + 64]) + red[threadIdx.x + 128]) + red[threadIdx.x + 192];
+}
+__global__ void colsum_final_kernel(const float* part, int slices, int cols, float* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  // all loads issued before the first add (clamped rows, then masked), the
+  // additions in slice order
+  float v[kColsumPart];
+#pragma unroll
+  for (int z = 0; z < kColsumPart; ++z) v[z] = part[static_cast<size_t>(min(z, slices - 1)) * cols + c];
+  float acc = 0.0f;
+#pragma unroll
+  for (int z = 0; z < kColsumPart; ++z) acc += z < slices ? v[z] : 0.0f;
+  out[c] = acc;
 }
 
 // AdamW on FP32 master parameters; refreshes the BF16 copy (W stored
@@ -558,6 +593,7 @@ __global__ void xmean_kernel(const float* in, const double* wx, float* out, int 
   const size_t q = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= inner) return;
   double s = 0.0, w = 0.0;
+#pragma unroll 8
   for (int o = 0; o < outer; ++o) {
     const double wo = wx[o];
     s += wo * in[static_cast<size_t>(o) * inner + q];
@@ -586,6 +622,8 @@ hipError_t launch_f64_to_f32(const double* in, float* out, size_t n, hipStream_t
 }
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
   const size_t total = static_cast<size_t>(a.Nx) * a.Nu * a.Nv * a.ld;
+  const size_t state = static_cast<size_t>(a.Nx) * a.Nu * a.Nv * a.n * a.n * a.n;
+  if (total > 0x7fffffff || state > 0x7fffffff) return hipErrorInvalidValue;   // 32-bit indices
   hipLaunchKernelGGL(gather_kernel, dim3(nblk(total, 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -596,7 +634,8 @@ hipError_t launch_gather_raw(const GatherArgs& a, float* out, hipStream_t s) {
 }
 hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s) {
   const size_t ne = static_cast<size_t>(a.Nx) * a.Nu * a.Nv;
-  hipLaunchKernelGGL(scatter_kernel, dim3(nblk(ne, 128)), dim3(128), 0, s, a);
+  if (ne > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scatter_kernel, dim3(static_cast<unsigned>(ne)), dim3(kWave), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
@@ -613,34 +652,48 @@ hipError_t launch_gemm_tiled(const GemmArgs& g, float* part, size_t part_floats,
   // the 16-byte loads need 16-byte aligned rows of the contiguous direction
   const size_t sa = ak ? g.sam : g.sak, sb = bn ? g.sbk : g.sbn;
   if (!(ak || am) || !(bn || bk) || !aligned16(g.A) || !aligned16(g.B) || (sa % 8) || (sb % 8)) return launch_gemm(g, s);
-  const int tiles = ((g.M + kTM - 1) / kTM) * ((g.N + kTN - 1) / kTN);
   // split K (the weight gradients: K = rows) until there are about two
-  // work-groups per CU, keeping slices of >= 256 so the reduction stays short
-  int slices = 1;
-  while (tiles * slices < 2 * cus && g.K / (2 * slices) >= 256) slices *= 2;
-  // each slice's k range must fit the kernel's register stage
+  // work-groups per CU, keeping slices of >= 256 so the reduction stays short;
+  // each slice's k range must also fit the kernel's register stage
   int smin = 1;
   while (static_cast<long long>(smin) * kMaxKT * kTK < g.K) smin *= 2;
-  slices = std::max(slices, smin);
+  auto split = [&](int tiles) {
+    int sl = 1;
+    while (tiles * sl < 2 * cus && g.K / (2 * sl) >= 256) sl *= 2;
+    return std::max(sl, smin);
+  };
+  // 64-row tiles while tiles x slices fill the CUs, else 32-row tiles (twice
+  // the work-groups)
+  int tm = kTM;
+  int tiles = ((g.M + tm - 1) / tm) * ((g.N + kTN - 1) / kTN);
+  int slices = split(tiles);
+  if (tiles * slices < cus) {
+    tm = kTM / 2;
+    tiles = ((g.M + tm - 1) / tm) * ((g.N + kTN - 1) / kTN);
+    slices = split(tiles);
+  }
   while (slices > smin && static_cast<size_t>(slices) * g.M * g.N > part_floats) slices /= 2;
   if (slices > 1 && static_cast<size_t>(slices) * g.M * g.N > part_floats) return launch_gemm(g, s);
   const int ks = ((g.K + slices - 1) / slices + kTK - 1) / kTK * kTK;
   slices = (g.K + ks - 1) / ks;
   if (ks > kMaxKT * kTK) return hipErrorInvalidValue;
   float* p = slices > 1 ? part : nullptr;
-  const dim3 grid((g.M + kTM - 1) / kTM, (g.N + kTN - 1) / kTN, slices);
-  if (ak && bn) hipLaunchKernelGGL((gemm_bf16_tiled_kernel<true, true>), grid, dim3(256), 0, s, g, p, ks);
-  else if (ak) hipLaunchKernelGGL((gemm_bf16_tiled_kernel<true, false>), grid, dim3(256), 0, s, g, p, ks);
-  else if (bn) hipLaunchKernelGGL((gemm_bf16_tiled_kernel<false, true>), grid, dim3(256), 0, s, g, p, ks);
-  else hipLaunchKernelGGL((gemm_bf16_tiled_kernel<false, false>), grid, dim3(256), 0, s, g, p, ks);
+  const dim3 grid((g.M + tm - 1) / tm, (g.N + kTN - 1) / kTN, slices);
+  if (tm == kTM) {
+    if (ak && bn) hipLaunchKernelGGL((gemm_bf16_tiled_kernel<true, true, kTM>), grid, dim3(256), 0, s, g, p, ks);
+    else if (ak) hipLaunchKernelGGL((gemm_bf16_tiled_kernel<true, false, kTM>), grid, dim3(256), 0, s, g, p, ks);
+    else if (bn) hipLaunchKernelGGL((gemm_bf16_tiled_kernel<false, true, kTM>), grid, dim3(256), 0, s, g, p, ks);
+    else hipLaunchKernelGGL((gemm_bf16_tiled_kernel<false, false, kTM>), grid, dim3(256), 0, s, g, p, ks);
+  } else {
+    if (ak && bn) hipLaunchKernelGGL((gemm_bf16_tiled_kernel<true, true, kTM / 2>), grid, dim3(256), 0, s, g, p, ks);
+    else if (ak) hipLaunchKernelGGL((gemm_bf16_tiled_kernel<true, false, kTM / 2>), grid, dim3(256), 0, s, g, p, ks);
+    else if (bn) hipLaunchKernelGGL((gemm_bf16_tiled_kernel<false, true, kTM / 2>), grid, dim3(256), 0, s, g, p, ks);
+    else hipLaunchKernelGGL((gemm_bf16_tiled_kernel<false, false, kTM / 2>), grid, dim3(256), 0, s, g, p, ks);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || slices == 1) return e;
   const size_t mn = static_cast<size_t>(g.M) * g.N;
   hipLaunchKernelGGL(gemm_reduce_kernel, dim3(nblk(mn, 256)), dim3(256), 0, s, part, slices, g);
-  return hipGetLastError();
-}
-hipError_t launch_bias_act(const BiasActArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(bias_act_kernel, dim3(nblk(static_cast<size_t>(a.rows) * a.ld, 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_gelu_back(const float* dA, const float* Z, float* dZ, uint16_t* dZb, int rows, int cols, int ld, hipStream_t s) {
@@ -652,8 +705,13 @@ hipError_t launch_mse(const float* Y, const float* T, int rows, int cols, int ld
   hipLaunchKernelGGL(mse_kernel, dim3(nblocks), dim3(256), 0, s, Y, T, rows, cols, ld, inv_count, dY, dYb, partial);
   return hipGetLastError();
 }
-hipError_t launch_colsum(const float* in, int rows, int cols, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(colsum_kernel, dim3(cols), dim3(256), 0, s, in, rows, cols, out);
+hipError_t launch_colsum(const float* in, int rows, int cols, float* out, float* part, hipStream_t s) {
+  const int per = (rows + kColsumPart - 1) / kColsumPart;   // at most kColsumPart slices
+  const int slices = (rows + per - 1) / per;
+  hipLaunchKernelGGL(colsum_part_kernel, dim3((cols + 63) / 64, slices), dim3(256), 0, s, in, rows, cols, per, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((cols + 255) / 256), dim3(256), 0, s, part, slices, cols, out);
   return hipGetLastError();
 }
 hipError_t launch_adamw(const AdamArgs& a, hipStream_t s) {

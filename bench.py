@@ -166,8 +166,8 @@ def bench_sweep(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="maxwell_1d2v_n9")
     ap.add_argument("--storage", default=None, help="override storage (f32/f64)")
     ap.add_argument("--layout", default=None, help="state layout: dense or vpad (1D2V only; the 1D2V default is vpad)")

@@ -42,20 +42,20 @@ __device__ __forceinline__ double dpp_f64(double v, int ctrl_sel) {
   i32x2 y;
   switch (ctrl_sel) {
     case 0:
-      y.x = __builtin_amdgcn_update_dpp(0, x.x, 0xB1, 0xF, 0xF, false);
-      y.y = __builtin_amdgcn_update_dpp(0, x.y, 0xB1, 0xF, 0xF, false);
+      y.x = __builtin_amdgcn_mov_dpp(x.x, 0xB1, 0xF, 0xF, true);
+      y.y = __builtin_amdgcn_mov_dpp(x.y, 0xB1, 0xF, 0xF, true);
       break;
     case 1:
-      y.x = __builtin_amdgcn_update_dpp(0, x.x, 0x4E, 0xF, 0xF, false);
-      y.y = __builtin_amdgcn_update_dpp(0, x.y, 0x4E, 0xF, 0xF, false);
+      y.x = __builtin_amdgcn_mov_dpp(x.x, 0x4E, 0xF, 0xF, true);
+      y.y = __builtin_amdgcn_mov_dpp(x.y, 0x4E, 0xF, 0xF, true);
       break;
     case 2:
-      y.x = __builtin_amdgcn_update_dpp(0, x.x, 0x124, 0xF, 0xF, false);
-      y.y = __builtin_amdgcn_update_dpp(0, x.y, 0x124, 0xF, 0xF, false);
+      y.x = __builtin_amdgcn_mov_dpp(x.x, 0x124, 0xF, 0xF, true);
+      y.y = __builtin_amdgcn_mov_dpp(x.y, 0x124, 0xF, 0xF, true);
       break;
     default:
-      y.x = __builtin_amdgcn_update_dpp(0, x.x, 0x128, 0xF, 0xF, false);
-      y.y = __builtin_amdgcn_update_dpp(0, x.y, 0x128, 0xF, 0xF, false);
+      y.x = __builtin_amdgcn_mov_dpp(x.x, 0x128, 0xF, 0xF, true);
+      y.y = __builtin_amdgcn_mov_dpp(x.y, 0x128, 0xF, 0xF, true);
       break;
   }
   return __builtin_bit_cast(double, y);
@@ -185,6 +185,13 @@ constexpr int lds_row() {
 }
 template <int N>
 constexpr int lds_words_2v() { return 3 * (N + 1) * lds_row<N>(); }
+// FP32 tiles with n >= 7 reduce their density partials through LDS once per
+// tile (N x 64 doubles); the others (FP64: LDS would cost occupancy; small n:
+// many resident tiles per CU) reduce each row with DPP.
+template <typename T, int N>
+constexpr bool dens_lds() { return sizeof(T) == 4 && N >= 7; }
+template <typename T, int N>
+constexpr int dens_words() { return dens_lds<T, N>() ? N * kWave : 1; }
 template <int N>
 constexpr int lds_words_1v() { return (N + 1) * lds_row<N>(); }
 
@@ -195,9 +202,10 @@ constexpr int lds_words_1v() { return (N + 1) * lds_row<N>(); }
 // padded).  UN: stage reads u^n.
 // -------------------------------------------------------------------------
 // lds: lds_words_2v<N>() words (input rows + 2 result buffers; row N of each
-// is the scratch row of idle lanes); hbuf: N*N words.
+// is the scratch row of idle lanes); hbuf: N*N words; dsum: dens_words<T, N>()
+// doubles.
 template <typename T, int N, bool UN>
-__device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* lds, T* hbuf) {
+__device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* lds, T* hbuf, double* dsum) {
   using B = Buf<T>;
   constexpr unsigned S = sizeof(T);
   constexpr int TV = kWave / N;
@@ -400,8 +408,13 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
     }
     if (a.partials) {
       // idle lanes: select, never multiply by a zero weight
-      sum = wave_sum(act ? sum * wvl : 0.0);
-      if (lane == 0) a.partials[static_cast<size_t>(ix * N + jx) * ntiles + iu * a.nvchunks + vc] = sum;
+      sum = act ? sum * wvl : 0.0;
+      if constexpr (dens_lds<T, N>()) {
+        dsum[jx * kWave + lane] = sum;   // reduced once per tile, after the last row
+      } else {
+        sum = wave_sum(sum);
+        if (lane == 0) a.partials[static_cast<size_t>(ix * N + jx) * ntiles + iu * a.nvchunks + vc] = sum;
+      }
     }
   };
 
@@ -460,13 +473,31 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   }
   wave_lds_order();
   finish_row(N - 1, accp, ((N - 1) & 1) ? lout1 : lout0);
+  if constexpr (dens_lds<T, N>()) {
+    if (a.partials) {
+      // lane 4r + q (r < N) adds the row-r partials of lanes 16q .. 16q+15 in
+      // lane order; the four quarters are then added in a fixed order
+      // ((q0 + q1) + (q2 + q3)) by two quad exchanges, and lane 4r writes.
+      wave_lds_order();
+      const int r = lane >> 2, q = lane & 3;
+      double t = 0.0;
+      if (r < N) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) t += dsum[r * kWave + 16 * q + i];
+      }
+      t += dpp_f64(t, 0);   // lane ^ 1
+      t += dpp_f64(t, 1);   // lane ^ 2
+      if (r < N && q == 0) a.partials[static_cast<size_t>(ix * N + r) * ntiles + iu * a.nvchunks + vc] = t;
+    }
+  }
 }
 
 template <typename T, int N, bool UN>
 __global__ void __launch_bounds__(kWave, 2) stage2v_kernel(StageArgs<T> a) {
   __shared__ T lds[lds_words_2v<N>()];
   __shared__ T hbuf[N * N];
-  stage2v_tile<T, N, UN>(a, xcd_remap(blockIdx.x, gridDim.x), lds, hbuf);
+  __shared__ double dsum[dens_words<T, N>()];
+  stage2v_tile<T, N, UN>(a, xcd_remap(blockIdx.x, gridDim.x), lds, hbuf, dsum);
 }
 
 // -------------------------------------------------------------------------
@@ -926,13 +957,14 @@ __global__ void __launch_bounds__(kWave, 2) stage_batched_kernel(const StageArgs
                                                                   const int* __restrict__ xcd_begin) {
   __shared__ float lds[NV == 2 ? lds_words_2v<N>() : lds_words_1v<N>()];
   __shared__ float hbuf[NV == 2 ? N * N : 1];
+  __shared__ double dsum[NV == 2 ? dens_words<float, N>() : 1];
   const int b = blockIdx.x, c = b & 7, slot = b >> 3, g = gridDim.x;
   const int slots = (g >> 3) + (c < (g & 7) ? 1 : 0);
   const int end = xcd_begin[c + 1];
   for (int i = xcd_begin[c] + slot; i < end; i += slots) {
     const int2 it = items[i];
     const StageArgs<float> a = runs[it.x];
-    if (NV == 2) stage2v_tile<float, N, UN>(a, it.y, lds, hbuf);
+    if (NV == 2) stage2v_tile<float, N, UN>(a, it.y, lds, hbuf, dsum);
     else stage1v_tile<float, N, UN>(a, it.y, lds);
     wave_lds_order();
   }

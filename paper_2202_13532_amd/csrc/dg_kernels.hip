@@ -492,8 +492,14 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   }
 }
 
+// FP64 slabs of n = 9 do not fit 256 VGPRs; at one wave per SIMD the
+// compiler may also use the accumulation registers instead of spilling to
+// scratch memory.
+template <typename T, int N>
+constexpr int stage_min_waves() { return sizeof(T) == 8 && N >= 9 ? 1 : 2; }
+
 template <typename T, int N, bool UN>
-__global__ void __launch_bounds__(kWave, 2) stage2v_kernel(StageArgs<T> a) {
+__global__ void __launch_bounds__(kWave, (stage_min_waves<T, N>())) stage2v_kernel(StageArgs<T> a) {
   __shared__ T lds[lds_words_2v<N>()];
   __shared__ T hbuf[N * N];
   __shared__ double dsum[dens_words<T, N>()];

@@ -44,6 +44,16 @@ def test_learned_correction_trains_and_runs():
     err_h = lc.relative_error(Xh, Th)
     print("held-out closure relative error", err_h, flush=True)
     assert err_h < 0.6
+    # minibatches of whole snapshots (4 per AdamW step) train as well
+    lc4 = learned.LearnedCorrection(learned.Config(train_seeds=[0, 1, 2, 3], snapshots_per_run=16,
+                                                   snapshot_stride=110, epochs=24, snapshots_per_step=4, lr=2e-3))
+    lc4.mean, lc4.inv_std, lc4.target_scale = lc.mean, lc.inv_std, lc.target_scale
+    lc4.init_params()
+    lc4.train(X, T)
+    err4 = lc4.relative_error(X, T)
+    print("training-set closure relative error, 4 snapshots per step:", err4, flush=True)
+    assert err4 < 0.5
+    lc4.close()
     ev = lc.evaluate(1000, 250, checkpoints=2)
     fe = ev["field_energy_rel_l2"]
     print("field energy rel L2", fe, "mass drift", ev["mass_drift"], flush=True)

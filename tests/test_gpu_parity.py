@@ -162,6 +162,29 @@ def test_steps_with_zero_speed_rows_match_oracle(vbc, storage):
         assert _rel_l2(out, fh) < F32_REL_L2
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_1d1v_zero_inflow_steps_match_oracle(storage):
+    # zero-inflow v boundaries with a field that changes sign: the v faces of
+    # the boundary elements take the zero outside value on inflow
+    nv, n, nelem, lo, hi = 1, 7, [3, 9], [0.0, -3.0], [2.0, 3.0]
+    print("1d1v zero inflow", storage, flush=True)
+    s, g = _setup(nv, n, nelem, lo, hi, 0.0, storage, "zero_inflow")
+    f = inputs.random_nodal(g.shape, 2024)
+    fd = _dev(f, s)
+    fh = _host(fd)
+    dt = 0.5 * s.dt_max(float(s.poisson(fd).abs().max()))
+    recs = s.step(fd, dt, 3, diag=True)
+    assert all(r["finite"] == 1 for r in recs)
+    ops = lgl.operators(n)
+    for _ in range(3):
+        fh = rk.ssprk3_step(g, ops, fh, dt)
+    out = _host(fd)
+    if storage == "f64":
+        assert _rel_max(out, fh) < F64_REL_MAX * 10
+    else:
+        assert _rel_l2(out, fh) < F32_REL_L2
+
+
 def test_landau_history_fp64_matches_oracle_and_conserves_mass():
     """Landau damping (x 16, v 32 elements, n = 4, FP64): 200 steps, dt = 0.01."""
     nv, n, nelem, lo, hi, wc = _landau_1d1v()

@@ -111,8 +111,9 @@ def bench_sweep(args):
     from paper_2202_13532_amd import dg
     from paper_2202_13532_amd import workloads as W
     wls = W.uneven_sweep(64)
-    cfgs = [dg.make_config(w.nv, w.n, w.nelem, w.lo, w.hi, w.omega_c) for w in wls]
-    solos = [dg.Solver(w.nv, w.n, w.nelem, w.lo, w.hi, w.omega_c) for w in wls]
+    lay = [(args.layout or "vpad") if w.nv == 2 else "dense" for w in wls]   # padded v rows for 1D2V runs
+    cfgs = [dg.make_config(w.nv, w.n, w.nelem, w.lo, w.hi, w.omega_c, layout=l) for w, l in zip(wls, lay)]
+    solos = [dg.Solver(w.nv, w.n, w.nelem, w.lo, w.hi, w.omega_c, layout=l) for w, l in zip(wls, lay)]
     states, dts = [], []
     for w, so in zip(wls, solos):
         f = make_state(torch, so, w)
@@ -150,6 +151,7 @@ def bench_sweep(args):
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "uneven_sweep_64", "runs": len(wls), "dof": dof, "storage": "f32",
+                   "layout_1d2v": args.layout or "vpad",
                    "reductions": "f64", "parallelism": "single GPU, one persistent launch per stage"},
         "hbm_effective_frac_whole_step": alg_bytes * args.steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "solo_sequential": {"ms_per_step": ms_solo / args.steps,

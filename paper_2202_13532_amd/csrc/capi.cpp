@@ -24,6 +24,9 @@ using dgi::Layout;
 namespace {
 
 constexpr size_t kAlign = 256;
+// Last-level (Infinity) cache of the GPU: stage outputs use non-temporal
+// stores when a run's three state buffers do not fit in it.
+constexpr size_t kLastLevelCache = size_t(256) << 20;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 std::mutex g_err_mu;
@@ -176,6 +179,7 @@ void fill_pack(const dg_ctx* c, dgk::StageArgs<T>* p, const void* fin, const voi
   a.nvchunks = L.nvchunks;
   a.cpitch = L.cpitch;
   a.lpitch = L.lpitch;
+  a.nt_store = 3 * L.selems * L.esize > kLastLevelCache ? 1 : 0;
   a.zero_inflow = c->cfg.vbc == DG_VBC_ZERO_INFLOW ? 1 : 0;
   a.Jx = static_cast<T>(2.0 / c->dx[0]);
   if (c->cfg.nv == 2) {
@@ -865,6 +869,10 @@ dg_status upload_args(dg_batch* b, void* const* f, const double* dt) {
       fill_field(c, &fa[k * b->nruns + r], E, nullptr, k == 2);
     }
   }
+  // the batch's runs share the cache: the store policy follows their total
+  size_t total = 0;
+  for (int r = 0; r < b->nruns; ++r) total += 3 * b->runs[r]->L.selems * b->runs[r]->L.esize;
+  for (auto& a : args) a.nt_store = total > kLastLevelCache ? 1 : 0;
   DGB_HIP(b, hipMemcpyAsync(b->d_args, args.data(), args.size() * sizeof(args[0]), hipMemcpyHostToDevice, b->stream));
   DGB_HIP(b, hipMemcpyAsync(b->d_fa, fa.data(), fa.size() * sizeof(fa[0]), hipMemcpyHostToDevice, b->stream));
   DGB_HIP(b, hipStreamSynchronize(b->stream));

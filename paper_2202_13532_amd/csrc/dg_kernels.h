@@ -31,6 +31,7 @@ struct StageArgs {
   double hu;              // du/2 (u-axis Jacobian inverse), nv = 2
   int Nx, Nu, Nv, nvchunks;
   int cpitch, lpitch;     // values per v chunk / per (x node, u node) row of the arrays
+  int nt_store;           // 1: non-temporal stores (the run's three state buffers exceed the last-level cache)
   int zero_inflow;        // 1: zero outside the velocity box
   T Jx, Ju, Jv, wc;       // Jacobians 2/dx per axis, omega_c
   T c_un, c_in, c_dt;     // stage coefficients

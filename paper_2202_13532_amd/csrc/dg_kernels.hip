@@ -134,11 +134,15 @@ __device__ __forceinline__ void contract(G g, T fL, T fR, T s, T* res) {
 
 // Raw buffer access.  A resource covers one x element of a state array; the
 // per-row offset goes in the scalar offset and the lane offset in the vector
-// offset.  Lanes past the ragged end of a v chunk get an out-of-range vector
+// offset.  st_nt stores with the non-temporal hint: a stage's output is read
+// only by the next kernel, and when the three state buffers exceed the
+// last-level (Infinity) cache, stores that allocate there leave dirty lines
+// whose write-back then competes with the next kernel's reads.  Lanes past the ragged end of a v chunk get an out-of-range vector
 // offset: the hardware range check returns 0 for their loads and drops their
 // stores, so no lane mask or branch is needed around memory operations.
 constexpr unsigned kRsrcWord3 = 0x00020000u;   // gfx9 raw-buffer format word
 constexpr unsigned kOffOOB = 0x80000000u;
+constexpr int kCpolNT = 2;                     // cache-policy operand: non-temporal
 
 template <typename T> struct Buf;
 template <> struct Buf<float> {
@@ -148,6 +152,9 @@ template <> struct Buf<float> {
   __device__ static void st(float v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, vo, so, 0);
   }
+  __device__ static void st_nt(float v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, vo, so, kCpolNT);
+  }
 };
 template <> struct Buf<double> {
   __device__ static double ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
@@ -156,6 +163,10 @@ template <> struct Buf<double> {
   __device__ static void st(double v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
     typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
+  }
+  __device__ static void st_nt(double v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, kCpolNT);
   }
 };
 
@@ -401,11 +412,15 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
     // density partial: (du/2) sum_ju w_ju v, reference weights as literals
     double sum = 0.0;
     const unsigned vj = vs + ((jx * NUn + iu * N) * LP + m0) * S;
+    if (a.nt_store) {   // uniform branch
 #pragma unroll
-    for (int ju = 0; ju < N; ++ju) {
-      B::st(act ? vout[ju] : T(0), ro, vj, ju * rowb);
-      sum = __builtin_fma(K.w[ju], static_cast<double>(vout[ju]), sum);
+      for (int ju = 0; ju < N; ++ju) B::st_nt(act ? vout[ju] : T(0), ro, vj, ju * rowb);
+    } else {
+#pragma unroll
+      for (int ju = 0; ju < N; ++ju) B::st(act ? vout[ju] : T(0), ro, vj, ju * rowb);
     }
+#pragma unroll
+    for (int ju = 0; ju < N; ++ju) sum = __builtin_fma(K.w[ju], static_cast<double>(vout[ju]), sum);
     if (a.partials) {
       // idle lanes: select, never multiply by a zero weight
       sum = act ? sum * wvl : 0.0;
@@ -597,7 +612,8 @@ __device__ __forceinline__ void stage1v_tile(const StageArgs<T> a, int bid, T* l
     const T rhs = acc[jx] + lds[jx * ROW + 1 + lane];
     const T base = UN ? fmadd(a.c_un, B::ld(ru, vo, soff(jx)) - f[jx], f[jx]) : a.c_in * f[jx];
     const T v = fmadd(a.c_dt, rhs, base);
-    B::st(v, ro, vo, soff(jx));
+    if (a.nt_store) B::st_nt(v, ro, vo, soff(jx));
+    else B::st(v, ro, vo, soff(jx));
     if (a.partials) {
       const double s = wave_sum(act ? wvl * static_cast<double>(v) : 0.0);
       if (lane == 0) a.partials[static_cast<size_t>(ix * N + jx) * a.nvchunks + vc] = s;

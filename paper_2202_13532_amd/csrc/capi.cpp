@@ -195,15 +195,17 @@ void fill_pack(const dg_ctx* c, dgk::StageArgs<T>* p, const void* fin, const voi
 
 // One fused stage kernel: out = c_un un + c_in fin + c_dt L(fin) (L with field E).
 dg_status stage(dg_ctx* c, const void* fin, const void* fun, void* out, const double* E,
-                double* partials, double c_un, double c_in, double c_dt) {
+                double* partials, double c_un, double c_in, double c_dt, bool reverse) {
   hipError_t e;
   if (c->f64()) {
     dgk::StageArgs<double> p;
     fill_pack(c, &p, fin, fun, out, E, partials, c_un, c_in, c_dt);
+    p.reverse = reverse ? 1 : 0;
     e = dgk::launch_stage(c->cfg.nv, c->L.n, true, &p, c->L.ntiles, c->stream);
   } else {
     dgk::StageArgs<float> p;
     fill_pack(c, &p, fin, fun, out, E, partials, c_un, c_in, c_dt);
+    p.reverse = reverse ? 1 : 0;
     e = dgk::launch_stage(c->cfg.nv, c->L.n, false, &p, c->L.ntiles, c->stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "stage kernel launch");
@@ -306,7 +308,8 @@ dg_status enqueue_step(dg_ctx* c, void* f, double dt, bool diag) {
   double* part = c->at<double>(c->L.off_part);
   DG_TRY(stage(c, f, nullptr, B, E, part, 0.0, 1.0, dt));
   DG_TRY(field(c, E, nullptr, false));
-  DG_TRY(stage(c, B, f, C, E, part, 0.75, 0.25, 0.25 * dt));
+  // stage 2 walks the tiles backwards (stage 1 wrote the last ones last)
+  DG_TRY(stage(c, B, f, C, E, part, 0.75, 0.25, 0.25 * dt, true));
   DG_TRY(field(c, E, nullptr, false));
   DG_TRY(stage(c, C, f, f, E, part, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt));
   DG_TRY(field(c, E, nullptr, diag));
@@ -652,7 +655,7 @@ dg_status dg_profile_step(dg_ctx* ctx, void* f, double dt, int32_t nsteps, doubl
     const double cu[3] = {0.0, 0.75, 1.0 / 3.0}, ci[3] = {1.0, 0.25, 2.0 / 3.0}, cd[3] = {dt, 0.25 * dt, 2.0 / 3.0 * dt};
     if (hipEventRecord(ev[0], ctx->stream) != hipSuccess) { st = fail(ctx, DG_ERR_DEVICE, "event record"); break; }
     for (int k = 0; k < 3 && st == DG_OK; ++k) {
-      st = stage(ctx, ins[k], f, outs[k], E, part, cu[k], ci[k], cd[k]);
+      st = stage(ctx, ins[k], f, outs[k], E, part, cu[k], ci[k], cd[k], k == 1);
       if (st == DG_OK && hipEventRecord(ev[2 * k + 1], ctx->stream) != hipSuccess) st = fail(ctx, DG_ERR_DEVICE, "event record");
       if (st == DG_OK) st = field(ctx, E, nullptr, false);
       if (st == DG_OK && hipEventRecord(ev[2 * k + 2], ctx->stream) != hipSuccess) st = fail(ctx, DG_ERR_DEVICE, "event record");

@@ -32,6 +32,7 @@ struct StageArgs {
   int Nx, Nu, Nv, nvchunks;
   int cpitch, lpitch;     // values per v chunk / per (x node, u node) row of the arrays
   int nt_store;           // 1: non-temporal stores (the run's three state buffers exceed the last-level cache)
+  int reverse;            // 1: 1D2V tiles visited in reverse order (single-run stage launches)
   int zero_inflow;        // 1: zero outside the velocity box
   T Jx, Ju, Jv, wc;       // Jacobians 2/dx per axis, omega_c
   T c_un, c_in, c_dt;     // stage coefficients

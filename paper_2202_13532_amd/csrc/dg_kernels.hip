@@ -518,7 +518,9 @@ __global__ void __launch_bounds__(kWave, (stage_min_waves<T, N>())) stage2v_kern
   __shared__ T lds[lds_words_2v<N>()];
   __shared__ T hbuf[N * N];
   __shared__ double dsum[dens_words<T, N>()];
-  stage2v_tile<T, N, UN>(a, xcd_remap(blockIdx.x, gridDim.x), lds, hbuf, dsum);
+  // reversed order: the tiles the previous stage wrote last are read first
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  stage2v_tile<T, N, UN>(a, a.reverse ? static_cast<int>(gridDim.x) - 1 - b : b, lds, hbuf, dsum);
 }
 
 // -------------------------------------------------------------------------

@@ -78,6 +78,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
+// Maximum over the 64 lanes (same exchange pattern), valid in every lane.
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_f64(v, 0));
+  v = fmax(v, dpp_f64(v, 1));
+  v = fmax(v, dpp_f64(v, 2));
+  v = fmax(v, dpp_f64(v, 3));
+  return fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), fmax(lane_f64(v, 32), lane_f64(v, 48)));
+}
+
 // The stage kernels run one wave per work-group.  LDS instructions of one
 // wave execute in program order, so exchanging data through LDS between the
 // lanes of that wave only needs the compiler not to reorder the accesses; a
@@ -832,14 +841,25 @@ __device__ __forceinline__ void fieldA_body(const FieldArgs& a, int ix) {
 __device__ __forceinline__ void fieldB_body(const FieldArgs& a) {
   extern __shared__ double csh[];          // 2 * pmax scaled coefficients
   __shared__ double red[2][kFieldB];
-  const int tid = threadIdx.x;
-  // c_p = sum over elements of the element partials: G groups of threads,
-  // each summing a contiguous G-th of the elements for one p (loads in
-  // flight), the groups' sums then added in order.
-  constexpr int G = 4;
-  for (int base = 0; base < a.pmax; base += kFieldB / G) {
-    const int p = base + tid % (kFieldB / G);
-    const int g = tid / (kFieldB / G);
+  __shared__ double wred[2][kFieldB / kWave];
+  __shared__ double mass_sh;
+  const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+  // mass: wave 0 adds the element partials (lane-strided, then a fixed
+  // exchange pattern) while the others start on the coefficients
+  if (wid == 0) {
+    double mp = 0.0;
+    for (int e = lane; e < a.Nx; e += kWave) mp += a.mpart[e];
+    mp = wave_sum(mp);
+    if (lane == 0) mass_sh = mp;
+  }
+  // c_p = sum over elements of the element partials, 64 modes at a time:
+  // G = 16 groups of threads, each adding a contiguous G-th of the elements
+  // for one mode (its loads in flight together), the groups' sums then added
+  // in order.
+  constexpr int PB = kWave, G = kFieldB / PB;
+  for (int base = 0; base < a.pmax; base += PB) {
+    const int p = base + tid % PB;
+    const int g = tid / PB;
     double cr = 0.0, ci = 0.0;
     if (p < a.pmax) {
       const int e0 = g * a.Nx / G, e1 = (g + 1) * a.Nx / G;
@@ -852,11 +872,11 @@ __device__ __forceinline__ void fieldB_body(const FieldArgs& a) {
     red[0][tid] = cr;
     red[1][tid] = ci;
     __syncthreads();
-    if (tid < kFieldB / G && base + tid < a.pmax) {
+    if (tid < PB && base + tid < a.pmax) {
       double r = 0.0, i = 0.0;
       for (int q = 0; q < G; ++q) {
-        r += red[0][q * (kFieldB / G) + tid];
-        i += red[1][q * (kFieldB / G) + tid];
+        r += red[0][q * PB + tid];
+        i += red[1][q * PB + tid];
       }
       if (a.coeffs) {
         a.coeffs[2 * (base + tid)] = r;
@@ -869,17 +889,6 @@ __device__ __forceinline__ void fieldB_body(const FieldArgs& a) {
     }
     __syncthreads();
   }
-  // mass: element partials reduced by a fixed tree
-  double mp = 0.0;
-  for (int e = tid; e < a.Nx; e += kFieldB) mp += a.mpart[e];
-  red[0][tid] = mp;
-  __syncthreads();
-  for (int w = kFieldB / 2; w > 0; w >>= 1) {
-    if (tid < w) red[0][tid] += red[0][tid + w];
-    __syncthreads();
-  }
-  const double mass = red[0][0];
-  __syncthreads();
   // E at every x node: the modes by the recurrence z_p = z_{p-1} z_1
   const int nodes = a.Nx * a.n;
   double fe = 0.0, mx = 0.0;
@@ -896,22 +905,25 @@ __device__ __forceinline__ void fieldB_body(const FieldArgs& a) {
     fe = __builtin_fma(a.wx[node] * e, e, fe);
     mx = fmax(mx, fabs(e));
   }
-  red[0][tid] = fe;
-  red[1][tid] = mx;
-  __syncthreads();
-  for (int w = kFieldB / 2; w > 0; w >>= 1) {
-    if (tid < w) {
-      red[0][tid] += red[0][tid + w];
-      red[1][tid] = fmax(red[1][tid], red[1][tid + w]);
-    }
-    __syncthreads();
+  // field energy and max |E|: per wave, then the waves in order
+  fe = wave_sum(fe);
+  mx = wave_max(mx);
+  if (lane == 0) {
+    wred[0][wid] = fe;
+    wred[1][wid] = mx;
   }
+  __syncthreads();
   if (tid == 0) {
-    const double m = mass;
-    const double fen = 0.5 * red[0][0];
-    const bool fin = isfinite(m) && isfinite(fen) && isfinite(red[1][0]);
+    double fsum = 0.0, fmx = 0.0;
+    for (int w = 0; w < kFieldB / kWave; ++w) {
+      fsum += wred[0][w];
+      fmx = fmax(fmx, wred[1][w]);
+    }
+    const double m = mass_sh;
+    const double fen = 0.5 * fsum;
+    const bool fin = isfinite(m) && isfinite(fen) && isfinite(fmx);
     const int k = (a.record && a.ring) ? *a.counter : -1;
-    double rec[8] = {0.0, m, fen, 0.0, 0.0, red[1][0], fin ? 1.0 : 0.0, static_cast<double>(k)};
+    double rec[8] = {0.0, m, fen, 0.0, 0.0, fmx, fin ? 1.0 : 0.0, static_cast<double>(k)};
     for (int q = 0; q < 8; ++q) a.last[q] = rec[q];
     if (k >= 0) {
       double* r = a.ring + 8 * (k % kRing);

@@ -262,8 +262,9 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   auto vrow = [&](int jx, int iue) -> unsigned { return vo + ((jx * NUn + iue * N) * LP + m0) * S; };
   // Store offset: the active lanes, plus the unused slots that end a padded
   // chunk, which receive zeros, so that every memory line of a row is written
-  // whole (a line left partly written costs the memory a read-modify-write).
-  // For dense rows this is exactly the active lanes.
+  // whole (left unwritten, the partly written lines made the padded layout
+  // slower than the dense one).  For dense rows this is exactly the active
+  // lanes.
   const unsigned vs = (lane < CP && m0 + lane < LP) ? lane * S : kOffOOB;
   const auto rf = xelem_rsrc(a.fin, xstride, ix, xbytes);
   const auto ru = xelem_rsrc(a.fun, xstride, ix, xbytes);

@@ -63,6 +63,7 @@ class Config:
     cfl_fraction: float = 0.9
     fluct: bool = False                # learn the closure of the fluctuation about the x average
     fp64_data: bool = True             # fine runs, projections and both RHS in FP64 (targets then FP32)
+    perturbation: float = 1e-3         # density perturbation amplitude of the initial states
 
 
 def run_parameters(seed):
@@ -101,7 +102,7 @@ class LearnedCorrection:
         p = run_parameters(seed)
         nodes = [t.from_numpy(self.fine.nodes(a)).to(self.device) for a in range(3)]
         x, u, v = inputs.broadcast_coords(nodes, t)
-        f = inputs.mixture(x, u, v, p["a"], p["vt"], 0.5, 1e-3, 3.0, t)
+        f = inputs.mixture(x, u, v, p["a"], p["vt"], 0.5, self.cfg.perturbation, 3.0, t)
         return f.to(self.fine.dtype).contiguous()
 
     def project(self, f_fine, out=None, coarse=None):
@@ -366,9 +367,10 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--fluct", action="store_true", help="fluctuation form (inputs and targets about the x average)")
     ap.add_argument("--fp32-data", action="store_true", help="fine runs, projections and right-hand sides in FP32")
+    ap.add_argument("--perturbation", type=float, default=1e-3, help="density perturbation amplitude")
     a = ap.parse_args(argv)
     cfg = Config(train_seeds=list(range(a.runs)), snapshots_per_run=a.snapshots, snapshot_stride=a.stride,
-                 epochs=a.epochs, fluct=a.fluct, fp64_data=not a.fp32_data)
+                 epochs=a.epochs, fluct=a.fluct, fp64_data=not a.fp32_data, perturbation=a.perturbation)
     log = lambda m: print(m, flush=True)  # noqa: E731
     lc = LearnedCorrection(cfg)
     t0 = time.perf_counter()

@@ -136,7 +136,8 @@ dg_status dg_poisson(dg_ctx* ctx, const void* f, double* E, double* coeffs);
  * m is max|E| of the initial state.  If host_diag != NULL it receives nsteps
  * records (state after each step) and the call waits; DG_ERR_NONFINITE is
  * returned if any record is non-finite.  The context's time t advances by
- * nsteps*dt.  Steps are replayed from a captured HIP graph.                 */
+ * nsteps*dt.  Pairs of steps are replayed from a captured HIP graph (an odd
+ * last step is launched directly).                                         */
 dg_status dg_rk_step(dg_ctx* ctx, void* f, double dt, int32_t nsteps, dg_diag* host_diag);
 
 /* Profiling form of dg_rk_step: the same nsteps steps, launched eagerly

@@ -301,17 +301,19 @@ dg_status leave(dg_ctx* c) {
 //   B = f + dt L(f);  C = 3/4 f + 1/4 (B + dt L(B));  f = 1/3 f + 2/3 (C + dt L(C)).
 // Each stage's density partials feed the next stage's field solve; the last
 // one gives the field of the new state (the next step's first stage).
-dg_status enqueue_step(dg_ctx* c, void* f, double dt, bool diag) {
+// One SSP-RK3 step.  The stages alternate the direction in which they visit
+// the tiles, so each starts with the tiles its predecessor wrote last; over a
+// pair of steps (odd = false, then true) every hand-over alternates.
+dg_status enqueue_step(dg_ctx* c, void* f, double dt, bool diag, bool odd) {
   void* B = c->ws + c->L.off_B;
   void* C = c->ws + c->L.off_C;
   double* E = c->at<double>(c->L.off_E);
   double* part = c->at<double>(c->L.off_part);
-  DG_TRY(stage(c, f, nullptr, B, E, part, 0.0, 1.0, dt));
+  DG_TRY(stage(c, f, nullptr, B, E, part, 0.0, 1.0, dt, odd));
   DG_TRY(field(c, E, nullptr, false));
-  // stage 2 walks the tiles backwards (stage 1 wrote the last ones last)
-  DG_TRY(stage(c, B, f, C, E, part, 0.75, 0.25, 0.25 * dt, true));
+  DG_TRY(stage(c, B, f, C, E, part, 0.75, 0.25, 0.25 * dt, !odd));
   DG_TRY(field(c, E, nullptr, false));
-  DG_TRY(stage(c, C, f, f, E, part, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt));
+  DG_TRY(stage(c, C, f, f, E, part, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0 * dt, odd));
   DG_TRY(field(c, E, nullptr, diag));
   if (diag) DG_TRY(moments(c, f));
   return DG_OK;
@@ -323,8 +325,10 @@ dg_status build_graph(dg_ctx* c, void* f, double dt, bool diag) {
     (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
   }
+  // the graph holds a pair of steps (the two tile-order patterns)
   DG_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  dg_status s = enqueue_step(c, f, dt, diag);
+  dg_status s = enqueue_step(c, f, dt, diag, false);
+  if (s == DG_OK) s = enqueue_step(c, f, dt, diag, true);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->stream, &g);
   if (s != DG_OK) {
@@ -607,7 +611,7 @@ dg_status dg_rk_step(dg_ctx* ctx, void* f, double dt, int32_t nsteps, dg_diag* h
   DG_TRY(begin_steps(ctx, f, dt, nsteps));
   const Layout& L = ctx->L;
   const bool diag = host_diag != nullptr;
-  DG_TRY(build_graph(ctx, f, dt, diag));
+  if (nsteps >= 2) DG_TRY(build_graph(ctx, f, dt, diag));
   int done = 0;
   bool bad = false;
   while (done < nsteps) {
@@ -616,7 +620,9 @@ dg_status dg_rk_step(dg_ctx* ctx, void* f, double dt, int32_t nsteps, dg_diag* h
       hipError_t e = dgk::launch_reset_counter(ctx->at<int>(L.off_ctr), ctx->stream);
       if (e != hipSuccess) return hip_fail(ctx, e, "counter reset");
     }
-    for (int s = 0; s < chunk; ++s) DG_HIP(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
+    int s = 0;
+    for (; s + 2 <= chunk; s += 2) DG_HIP(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
+    if (s < chunk) DG_TRY(enqueue_step(ctx, f, dt, diag, false));   // odd count: last step eagerly
     if (diag) {
       std::vector<double> ring(static_cast<size_t>(chunk) * 8);
       DG_HIP(ctx, hipMemcpyAsync(ring.data(), ctx->at<double>(L.off_ring), ring.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
@@ -655,7 +661,7 @@ dg_status dg_profile_step(dg_ctx* ctx, void* f, double dt, int32_t nsteps, doubl
     const double cu[3] = {0.0, 0.75, 1.0 / 3.0}, ci[3] = {1.0, 0.25, 2.0 / 3.0}, cd[3] = {dt, 0.25 * dt, 2.0 / 3.0 * dt};
     if (hipEventRecord(ev[0], ctx->stream) != hipSuccess) { st = fail(ctx, DG_ERR_DEVICE, "event record"); break; }
     for (int k = 0; k < 3 && st == DG_OK; ++k) {
-      st = stage(ctx, ins[k], f, outs[k], E, part, cu[k], ci[k], cd[k], k == 1);
+      st = stage(ctx, ins[k], f, outs[k], E, part, cu[k], ci[k], cd[k], (k == 1) != (s % 2 == 1));   // as enqueue_step
       if (st == DG_OK && hipEventRecord(ev[2 * k + 1], ctx->stream) != hipSuccess) st = fail(ctx, DG_ERR_DEVICE, "event record");
       if (st == DG_OK) st = field(ctx, E, nullptr, false);
       if (st == DG_OK && hipEventRecord(ev[2 * k + 2], ctx->stream) != hipSuccess) st = fail(ctx, DG_ERR_DEVICE, "event record");

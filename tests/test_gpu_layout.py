@@ -168,3 +168,19 @@ def test_vpad_rejected_by_learned_correction_calls():
     with pytest.raises(dg.DGError, match="DG_LAYOUT_DENSE"):
         dg.dg_nn_features_raw(p.ctx, f, E, out)
     p.close()
+
+
+def test_layout_calls_reject_bad_arguments():
+    case = CASES[0]
+    n, nelem, lo, hi, wc, vbc = case
+    p = dg.Solver(2, n, nelem, lo, hi, wc, 0, "f32", vbc, layout="vpad")
+    f = _state(case, p, 5)
+    with pytest.raises(dg.DGError, match="NULL"):
+        dg.dg_state_pack(p.ctx, None, p.empty_state())
+    with pytest.raises(dg.DGError, match="NULL"):
+        dg.dg_state_unpack(p.ctx, p.pack(f), None)
+    with pytest.raises(dg.DGError):
+        p.pack(f[:, :, :, :, :-1].contiguous())          # wrong dense shape
+    with pytest.raises(dg.DGError):
+        p.step(f, 1e-3, 1)                              # a dense array is not a padded state
+    p.close()

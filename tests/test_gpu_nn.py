@@ -75,7 +75,8 @@ def _cos(a, b):
     return float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * np.linalg.norm(b)))
 
 
-@pytest.mark.parametrize("rows,k,n", [(37, 40, 24), (1000, 452, 128), (4133, 128, 64), (5, 3, 1)])
+# (16384, 452, 128) takes the 64-row tiles, the others the 32-row tiles
+@pytest.mark.parametrize("rows,k,n", [(37, 40, 24), (1000, 452, 128), (4133, 128, 64), (5, 3, 1), (16384, 452, 128)])
 def test_mfma_gemm_exact_on_integer_operands(rows, k, n):
     print("gemm exact", rows, k, n, flush=True)
     rng = np.random.default_rng(rows + k + n)
@@ -91,7 +92,8 @@ def test_mfma_gemm_exact_on_integer_operands(rows, k, n):
     net.close()
 
 
-@pytest.mark.parametrize("rows,k,n", [(256, 40, 32), (1024, 452, 64), (128, 128, 128)])
+# (8192, 452, 128): 64-row tiles and 16 k slices of 512 rows
+@pytest.mark.parametrize("rows,k,n", [(256, 40, 32), (1024, 452, 64), (128, 128, 128), (8192, 452, 128)])
 def test_weight_gradient_gemm_exact_on_integer_operands(rows, k, n):
     """One linear layer with integer data and rows * n a power of two: every
     value of dY = 2 (Y - T) / (rows n) is exact in BF16 and every sum exact in

@@ -332,7 +332,7 @@ dg_status build_graph(dg_ctx* c, void* f, double dt, bool diag) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->stream, &g);
   if (s != DG_OK) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return s;
   }
   if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
@@ -420,9 +420,9 @@ dg_status make_ctx(const dg_config* cfg, char* ws, hipStream_t user, bool own_st
   auto cleanup = [&](hipError_t e, const char* what) {
     *err = std::string(what) + ": " + hipGetErrorString(e);
     if (c->owns_stream) {
-      if (c->stream) hipStreamDestroy(c->stream);
-      if (c->ev_in) hipEventDestroy(c->ev_in);
-      if (c->ev_out) hipEventDestroy(c->ev_out);
+      if (c->stream) (void)hipStreamDestroy(c->stream);
+      if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+      if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     }
     delete c;
     return DG_ERR_DEVICE;
@@ -518,7 +518,7 @@ dg_status dg_init(const dg_config* cfg, void* workspace, size_t workspace_bytes,
 dg_status dg_destroy(dg_ctx* ctx) {
   if (!ctx) return DG_OK;
   hipError_t e = hipStreamSynchronize(ctx->stream);
-  if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
   if (ctx->owns_stream) {
     (void)hipEventDestroy(ctx->ev_in);
     (void)hipEventDestroy(ctx->ev_out);
@@ -674,7 +674,7 @@ dg_status dg_profile_step(dg_ctx* ctx, void* f, double dt, int32_t nsteps, doubl
       host_ms[6 * s + q] = ms;
     }
   }
-  for (auto& e : ev) hipEventDestroy(e);
+  for (auto& e : ev) (void)hipEventDestroy(e);
   if (st != DG_OK) return st;
   ctx->t += nsteps * dt;
   return leave(ctx);
@@ -925,7 +925,7 @@ dg_status build_batch_graph(dg_batch* b, void* const* f, const double* dt, bool 
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(b->stream, &g);
   if (s != DG_OK) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return s;
   }
   if (e != hipSuccess) return bfail(b, DG_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
@@ -1016,9 +1016,9 @@ dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, s
   b->run_off = BL.run_off;
   auto cleanup = [&](dg_status s, const std::string& m) {
     for (dg_ctx* c : b->runs) delete c;
-    if (b->stream) hipStreamDestroy(b->stream);
-    if (b->ev_in) hipEventDestroy(b->ev_in);
-    if (b->ev_out) hipEventDestroy(b->ev_out);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     delete b;
     return init_fail(s, m);
   };
@@ -1100,8 +1100,8 @@ dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, s
 dg_status dg_batch_destroy(dg_batch* b) {
   if (!b) return DG_OK;
   hipError_t e = hipStreamSynchronize(b->stream);
-  if (b->gexec) hipGraphExecDestroy(b->gexec);
-  for (dg_ctx* c : b->runs) dg_destroy(c);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  for (dg_ctx* c : b->runs) (void)dg_destroy(c);
   (void)hipEventDestroy(b->ev_in);
   (void)hipEventDestroy(b->ev_out);
   (void)hipStreamDestroy(b->stream);

@@ -22,6 +22,8 @@ paper's definitions, in float64:
 * ``mlp``        -- FP64 MLP forward/backward used to check the learned
                     correction's gradients.
 * ``projection`` -- L2 projection between DG grids (fine -> coarse).
+* ``harris``     -- Harris dispersion function of the loss-cone ring and its
+                    roots (Sec. 4.1), for the paper's case studies.
 * ``brute``      -- tiny-grid dense assembly of the weak form by quadrature in
                     all dimensions at once, used only to pin ``rhs``.
 

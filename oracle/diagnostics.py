@@ -9,7 +9,9 @@ L2 norm int f^2, all by the product LGL rule (exact for the interpolant's
 polynomial integrands up to degree 2n-3 per axis).
 
 Pinned by tests/test_oracle_diag.py: the ring-distribution moments of App. B
-(closed forms with Gamma functions) and Gaussian moments.
+(closed forms with Gamma functions), Gaussian moments, and the field energy of
+a linear field (exactly L^3/6: pins the factor 1/2 and the weights w dx/2) and
+of a single Fourier mode (A^2 L/4).
 """
 import numpy as np
 

@@ -10,7 +10,10 @@ X is (rows, in), W is (in, out), so y = X W + b.
 Pinned by tests/test_oracle_mlp.py: central finite differences of the loss
 for every parameter tensor and the input, GELU against its definition and
 its derivative by finite differences, AdamW against a hand-expanded first
-step.
+step and against three steps with different gradients written out with the
+moment recurrences unrolled (from the second step on the bias-corrected
+moments differ from g and g^2, so the roles of beta1 and beta2 and the
+bias-correction exponents are fixed).
 """
 import math
 

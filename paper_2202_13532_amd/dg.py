@@ -315,8 +315,17 @@ class Solver:
         dg_state_unpack(self.ctx, f, out)
         return out
 
+    def _check_field(self, E):
+        t = self.torch
+        nx = self.nelem[0] * self.n
+        if (not isinstance(E, t.Tensor) or E.device.type != "cuda" or E.dtype != t.float64
+                or not E.is_contiguous() or E.numel() != nx):
+            raise DGError(DG_ERR_INVALID, "E must be a contiguous float64 device tensor of %d values" % nx)
+
     def rhs(self, f, E=None, out=None):
         self._check_state(f)
+        if E is not None:
+            self._check_field(E)
         out = self.empty_state() if out is None else out
         self._check_state(out)
         dg_rhs(self.ctx, f, E, out)
@@ -374,8 +383,15 @@ def _ptr_array(states):
     return (ctypes.c_void_p * len(states))(*[t.data_ptr() for t in states])
 
 
+def _batch_dts(states, dts):
+    dt = np.ascontiguousarray(dts, dtype=np.float64).reshape(-1)
+    if dt.size != len(states):
+        raise DGError(DG_ERR_INVALID, "need one dt per run (%d runs, %d dt values)" % (len(states), dt.size))
+    return dt
+
+
 def dg_batch_rk_step(b, states, dts, nsteps, diag=False):
-    dt = np.ascontiguousarray(dts, dtype=np.float64)
+    dt = _batch_dts(states, dts)
     recs = (dg_diag * (len(states) * nsteps))() if (diag and nsteps > 0) else None
     _bcheck(lib().dg_batch_rk_step(b, _ptr_array(states), _dptr(dt), int(nsteps), recs), b)
     if recs is None:
@@ -384,7 +400,7 @@ def dg_batch_rk_step(b, states, dts, nsteps, diag=False):
 
 
 def dg_batch_tune(b, states, dts, reps):
-    dt = np.ascontiguousarray(dts, dtype=np.float64)
+    dt = _batch_dts(states, dts)
     best = np.zeros(1)
     _bcheck(lib().dg_batch_tune(b, _ptr_array(states), _dptr(dt), int(reps), _dptr(best)), b)
     return float(best[0])

@@ -14,6 +14,11 @@ Workloads (sizes and recipes are listed in ``workloads``):
   * maxwell_multimode -- exp(-(u^2+v^2)/2)/(2 pi) [1 + eps sum_p cos(p k1 x + phi_p)]
                    with phases phi_p ~ U[0, 2 pi) from numpy's default_rng(seed).
   * random_nodal -- U(0, 1) at every node (parity of the linear operator).
+  * loss_cone   -- the ring of eq. loss_cone, (s^j e^{-s}) / (2 pi alpha^2 j!),
+                   s = v_perp^2 / (2 alpha^2)                           (1D2V)
+  * cyclotron_mode -- the linear eigenmode of eq. ic about loss_cone (Sec. 4.1):
+                   (f0'(v_perp)/v_perp) Re(psi), psi a 2 nmax + 1 term Bessel
+                   sum, for a given root (k, omega) of the dispersion relation.
 """
 import math
 
@@ -70,6 +75,43 @@ def random_field(nx_nodes, seed, scale=0.3):
 def mixture(x, u, v, a, vt, k1, eps=1e-3, r0=3.0, xp=np):
     """a ring(r0) + (1 - a) Maxwellian(vt), times (1 + eps cos(k1 x))."""
     return (a * ring(u, v, r0, xp) + (1.0 - a) * maxwellian_2d(u, v, vt, xp)) * (1.0 + eps * xp.cos(k1 * x))
+
+
+def loss_cone(u, v, j=6, alpha=1.0, xp=np):
+    s = (u * u + v * v) / (2.0 * alpha * alpha)
+    return s ** j * xp.exp(-s) / (2.0 * math.pi * alpha * alpha * math.factorial(j))
+
+
+def cyclotron_mode(x, u, v, kx, k0, omega, j=6, alpha=1.0, nmax=20, sense=-1.0, complex_out=False):
+    """Eigenmode of eq. ic for the ring of eq. loss_cone (NumPy, FP64).
+
+    psi = exp(i (kx x + k0 v_perp sin phi)) sum_{|m| <= nmax} m / (m - omega)
+    J_m(k0 v_perp) e^{-i m phi};  f1 = (f0'(v_perp) / v_perp) Re(psi), with
+    f0'/v_perp = (j - v_perp^2 / (2 alpha^2)) f0 / v_perp^2 (the radial
+    gradient of eq. loss_cone).  kx is the wavenumber in units of the x
+    coordinate, k0 = kx v_t / omega_c the same wavenumber in inverse Larmor
+    radii (the argument of the Bessel functions), omega the root in units of
+    the cyclotron frequency.  The angle is phi = atan2(sense v, u): with the
+    force F = [u, -E - v B, u B] of this library (B > 0) the gyration runs
+    clockwise in (u, v), which the printed mode describes with sense = -1.
+    Returns f1 with unit-free amplitude (the caller scales it), or the
+    complex (f0'/v_perp) psi when complex_out.
+    """
+    from scipy import special
+    vp = np.sqrt(u * u + v * v)
+    vps = np.where(vp > 0.0, vp, 1.0)
+    phi = np.arctan2(sense * v, u)
+    s = vp * vp / (2.0 * alpha * alpha)
+    f0 = s ** j * np.exp(-s) / (2.0 * math.pi * alpha * alpha * math.factorial(j))
+    grad = np.where(vp > 0.0, (j - s) * f0 / (vps * vps), 0.0)
+    arg = k0 * vp
+    acc = np.zeros(np.broadcast(x, u, v).shape, dtype=np.complex128)
+    for m in range(-nmax, nmax + 1):
+        if m == 0:
+            continue
+        acc = acc + (m / (m - omega)) * special.jv(m, arg) * np.exp(-1j * m * phi)
+    psi = np.exp(1j * (kx * x + k0 * vp * np.sin(phi))) * acc
+    return grad * psi if complex_out else grad * psi.real
 
 
 def broadcast_coords(axes_nodes, xp=np):

@@ -6,13 +6,15 @@ import pytest
 import scipy.special as sp
 
 from oracle import lgl
+from tests.golden import paper_value
 
 
 def test_textbook_node_sets():
-    # n = 3: {-1, 0, 1}, weights {1/3, 4/3, 1/3}
+    # n = 3: {-1, 0, 1}, weights {1/3, 4/3, 1/3} (stored with its citation)
     x, w = lgl.lgl_nodes_weights(3)
-    assert np.allclose(x, [-1, 0, 1], atol=1e-15)
-    assert np.allclose(w, [1 / 3, 4 / 3, 1 / 3], atol=1e-15)
+    g = paper_value("lgl_n3")
+    assert np.allclose(x, g["nodes"], atol=1e-15)
+    assert np.allclose(w, g["weights"], atol=1e-15)
     # n = 4: {+-1, +-1/sqrt5}, weights {1/6, 5/6}
     x, w = lgl.lgl_nodes_weights(4)
     s = 1 / math.sqrt(5)

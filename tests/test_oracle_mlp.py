@@ -58,6 +58,45 @@ def test_adamw_first_step():
     assert np.allclose(out[0], exp_w, atol=1e-15) and np.allclose(out[1], exp_b, atol=1e-15)
 
 
+def test_adamw_three_steps_hand_expanded():
+    # Three steps with different gradients, written out with the moment
+    # recurrences unrolled: m_t = (1-b1) sum_s b1^(t-s) g_s and
+    # v_t = (1-b2) sum_s b2^(t-s) g_s^2, bias-corrected by 1 - b^t.  From t = 2
+    # on m_hat != g and v_hat != g^2, so a swapped b1/b2, a wrong exponent in
+    # the bias correction or decay on the bias term changes the result.
+    b1, b2, eps, lr, wd = 0.9, 0.999, 1e-8, 0.05, 0.2
+    w0, c0 = np.array([[0.7, -1.1, 0.25]]), np.array([0.3])
+    gw = [np.array([[0.5, -0.2, 1.0]]), np.array([[-0.3, 0.4, 0.1]]), np.array([[0.2, 0.2, -0.6]])]
+    gb = [np.array([1.5]), np.array([-0.5]), np.array([0.25])]
+    params = [w0.copy(), c0.copy()]
+    m = [np.zeros_like(w0), np.zeros_like(c0)]
+    v = [np.zeros_like(w0), np.zeros_like(c0)]
+    for t in (1, 2, 3):
+        params = mlp.adamw_step(params, [gw[t - 1], gb[t - 1]], m, v, t, lr=lr, b1=b1, b2=b2, eps=eps, wd=wd)
+    # hand expansion
+    w, c = w0.copy(), c0.copy()
+    for t in (1, 2, 3):
+        mw = (1 - b1) * sum(b1 ** (t - s) * gw[s - 1] for s in range(1, t + 1))
+        vw = (1 - b2) * sum(b2 ** (t - s) * gw[s - 1] ** 2 for s in range(1, t + 1))
+        mb = (1 - b1) * sum(b1 ** (t - s) * gb[s - 1] for s in range(1, t + 1))
+        vb = (1 - b2) * sum(b2 ** (t - s) * gb[s - 1] ** 2 for s in range(1, t + 1))
+        w = w - lr * ((mw / (1 - b1 ** t)) / (np.sqrt(vw / (1 - b2 ** t)) + eps) + wd * w)
+        c = c - lr * ((mb / (1 - b1 ** t)) / (np.sqrt(vb / (1 - b2 ** t)) + eps))
+    assert np.max(np.abs(params[0] - w)) < 1e-14 and np.max(np.abs(params[1] - c)) < 1e-14
+    # the step-2 bias term, worked by hand: m = 0.09*1.5 + 0.1*(-0.5) = 0.085,
+    # v = 0.999*0.001*2.25 + 0.001*0.25 = 0.00249775; m_hat = 0.085/0.19,
+    # v_hat = 0.00249775/0.001999
+    p2 = [w0.copy(), c0.copy()]
+    m2 = [np.zeros_like(w0), np.zeros_like(c0)]
+    v2 = [np.zeros_like(w0), np.zeros_like(c0)]
+    for t in (1, 2):
+        p2 = mlp.adamw_step(p2, [gw[t - 1], gb[t - 1]], m2, v2, t, lr=lr, b1=b1, b2=b2, eps=eps, wd=wd)
+    assert abs(m2[1][0] - 0.085) < 1e-15 and abs(v2[1][0] - 0.00249775) < 1e-15
+    step1 = 1.5 / (1.5 + eps)
+    step2 = (0.085 / 0.19) / (math.sqrt(0.00249775 / 0.001999) + eps)
+    assert abs(p2[1][0] - (0.3 - lr * step1 - lr * step2)) < 1e-14
+
+
 @pytest.mark.parametrize("nc,nf,r", [(4, 8, 2), (3, 5, 3), (4, 4, 2), (2, 6, 4)])
 def test_projection_exact_on_coarse_polynomials(nc, nf, r):
     # f = polynomial of degree nc-1 in x on each coarse element is reproduced exactly

@@ -6,6 +6,7 @@ import pytest
 import scipy.special as sp
 
 from oracle import grid, lgl, poisson
+from tests.golden import paper_value
 
 
 @pytest.mark.parametrize("n,N", [(2, 7), (3, 10), (5, 6), (8, 12)])
@@ -75,9 +76,10 @@ def test_poisson_sine_hp_convergence(n):
     """Phi'' = sin(2 pi x): error falls like dx^(n+1/2) (Sec. 5.3.2, Poisson figure)."""
     Ns = [10, 15, 20, 25]
     e = np.array([_poisson_errors(n, N) for N in Ns])
+    order = n + paper_value("poisson_convergence_order_offset")["value"]   # n + 1/2
     for col in range(2):
         slope = -np.polyfit(np.log(Ns), np.log(e[:, col]), 1)[0]
-        assert n + 0.3 < slope < n + 0.75, (n, col, slope, e[:, col])
+        assert order - 0.2 < slope < order + 0.25, (n, col, slope, e[:, col])
     assert e[-1, 1] < 1e-4
 
 

@@ -126,6 +126,24 @@ dg_status dg_destroy(dg_ctx* ctx);
  * they must not overlap.                                                    */
 dg_status dg_rhs(dg_ctx* ctx, const void* f, const double* E, void* rhs);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: dg_rhs with
+ * no context and no workspace.  rhs <- L(f) for the configuration cfg
+ * (copied; checked as by dg_init), with the field E (Nx*n doubles, device) or,
+ * if E == NULL, the field solved from f.  The call enqueues on hip_stream
+ * (a hipStream_t; NULL = the legacy default stream) and returns without
+ * waiting; it calls no hipMalloc / hipFree and copies nothing from the host.
+ * Scratch (node tables and connection tensor, rebuilt by a device kernel on
+ * every call, density and Fourier partials, E) lives in a library-owned
+ * array of DG_RHS_STATIC_SCRATCH_BYTES bytes per GPU, held until the process
+ * ends: configurations needing more are rejected with DG_ERR_OOM.  Every
+ * call on a GPU uses that GPU's one array, so calls that overlap on one GPU
+ * (concurrent streams or threads) race; calls on one stream are ordered.
+ * Errors are read with dg_last_error(NULL).  Results equal dg_rhs's up to
+ * the rounding of the device-built tables.                                 */
+#define DG_RHS_STATIC_SCRATCH_BYTES ((size_t)8 << 20)
+dg_status dg_rhs_static(const dg_config* cfg, const void* f, const double* E, void* rhs, void* hip_stream);
+
 /* E <- field of f (Nx*n doubles, device).  If coeffs != NULL it receives the
  * Fourier coefficients c_p, p = 1..pmax, as 2*pmax doubles (re, im) of the
  * source n - 1 (eq. spectral_transform, eq. electric_sol).                  */

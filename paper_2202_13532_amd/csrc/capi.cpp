@@ -50,7 +50,9 @@ const char* validate(const dg_config* c) {
   return nullptr;
 }
 
-Layout make_layout(const dg_config* c) {
+// Workspace layout.  Without stage buffers (the allocation-free entry point)
+// B and C are not reserved and the diagnostics ring holds one record.
+Layout make_layout(const dg_config* c, bool stage_buffers = true) {
   Layout L;
   L.n = c->n;
   L.naxes = 1 + c->nv;
@@ -71,8 +73,8 @@ Layout make_layout(const dg_config* c) {
   const size_t nx = static_cast<size_t>(L.Nx) * L.n;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
-  L.off_B = take(L.selems * L.esize);
-  L.off_C = take(L.selems * L.esize);
+  L.off_B = take(stage_buffers ? L.selems * L.esize : 0);
+  L.off_C = take(stage_buffers ? L.selems * L.esize : 0);
   L.off_part = take(nx * L.ntiles_slab * 8);
   L.off_mom = take(static_cast<size_t>(L.ntiles) * 4 * 8);
   L.off_dens = take(nx * 8);
@@ -80,7 +82,7 @@ Layout make_layout(const dg_config* c) {
   L.off_cpart = take(static_cast<size_t>(L.Nx) * L.pmax * 16);
   L.off_mpart = take(static_cast<size_t>(L.Nx) * 8);
   L.off_coef = take(static_cast<size_t>(L.pmax) * 16);
-  L.off_ring = take(static_cast<size_t>(dgk::kRing) * 64);
+  L.off_ring = take(static_cast<size_t>(stage_buffers ? dgk::kRing : 1) * 64);
   L.off_last = take(64);
   L.off_ctr = take(sizeof(int));
   L.off_T = take(static_cast<size_t>(L.pmax) * nx * 16);
@@ -346,6 +348,16 @@ dg_status build_graph(dg_ctx* c, void* f, double dt, bool diag) {
   c->g_dt = dt;
   c->g_diag = diag;
   return DG_OK;
+}
+
+Layout scratch_layout(const dg_config* cfg) { return make_layout(cfg, false); }
+
+const char* config_error(const dg_config* cfg, dg_status* st) { return check_cfg(cfg, st); }
+
+dg_status global_fail(dg_status s, const std::string& msg) {
+  std::lock_guard<std::mutex> lk(g_err_mu);
+  g_init_error = msg;
+  return s;
 }
 
 void copy_record(const double* r, double t, dg_diag* out) {

@@ -68,5 +68,11 @@ dg_status leave(dg_ctx* c);
 // Field of f, CFL check of dt (synchronises).
 dg_status begin_steps(dg_ctx* ctx, void* f, double dt, int32_t nsteps);
 void copy_record(const double* r, double t, dg_diag* out);
+// Workspace layout without stage buffers (the stage's scratch only).
+Layout scratch_layout(const dg_config* cfg);
+// Reason cfg is rejected (and the status in *st), or NULL.
+const char* config_error(const dg_config* cfg, dg_status* st);
+// Record msg as the context-free error (dg_last_error(NULL)) and return s.
+dg_status global_fail(dg_status s, const std::string& msg);
 
 }  // namespace dgi

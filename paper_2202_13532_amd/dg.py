@@ -27,7 +27,7 @@ EXPORTED = ["dg_workspace_bytes", "dg_init", "dg_destroy", "dg_rhs", "dg_poisson
             "dg_nn_set_params", "dg_nn_get_params", "dg_nn_forward", "dg_nn_loss_grad", "dg_nn_adamw",
             "dg_projection_matrix", "dg_project", "dg_nn_features", "dg_nn_features_raw", "dg_nn_to_elements",
             "dg_nn_column_stats", "dg_nn_rk_step", "dg_nn_last_error", "dg_state_elems", "dg_state_pack",
-            "dg_state_unpack"]
+            "dg_state_unpack", "dg_rhs_static"]
 
 
 class dg_config(ctypes.Structure):
@@ -112,6 +112,7 @@ def lib():
         "dg_state_elems": (S, [P]),
         "dg_state_pack": (I, [P, P, P]),
         "dg_state_unpack": (I, [P, P, P]),
+        "dg_rhs_static": (I, [cfgp, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -180,6 +181,10 @@ def dg_destroy(ctx):
 
 def dg_rhs(ctx, f, E, rhs):
     _check(lib().dg_rhs(ctx, _ptr(f), _ptr(E), _ptr(rhs)), ctx)
+
+
+def dg_rhs_static(cfg, f, E, rhs, stream=None):
+    _check(lib().dg_rhs_static(ctypes.byref(cfg), _ptr(f), _ptr(E), _ptr(rhs), ctypes.c_void_p(stream)), None)
 
 
 def dg_poisson(ctx, f, E, coeffs=None):

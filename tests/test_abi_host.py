@@ -150,3 +150,21 @@ def test_network_workspace_and_init_validation():
     assert "workspace" in dg.dg_nn_last_error(None)
     assert L.dg_nn_init(arr, 0, 4096, None, nb, None, dg.ctypes.byref(out)) == dg.DG_ERR_INVALID
     assert L.dg_nn_param_count(None) == 0
+
+
+def test_rhs_static_checks_before_touching_the_device():
+    """dg_rhs_static rejects bad arguments and configurations beyond its
+    scratch array on the host, before any device call (the pointers below are
+    never dereferenced)."""
+    import ctypes
+    L = _lib()
+    fake_f, fake_out = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    big = dg.make_config(2, 9, [256, 48, 48], [0.0, -8.0, -8.0], [1.0, 8.0, 8.0], 1.0)
+    assert L.dg_rhs_static(ctypes.byref(big), fake_f, None, fake_out, None) == dg.DG_ERR_OOM
+    msg = dg.dg_last_error(None)
+    assert "dg_rhs_static" in msg and "maximum of 8388608 bytes" in msg
+    ok = dg.make_config(2, 4, [3, 4, 5], [0.0, -6.0, -6.0], [1.0, 6.0, 6.0], 1.0)
+    assert L.dg_rhs_static(ctypes.byref(ok), None, None, fake_out, None) == dg.DG_ERR_INVALID
+    assert L.dg_rhs_static(ctypes.byref(ok), fake_f, None, fake_f, None) == dg.DG_ERR_INVALID
+    bad = dg.make_config(3, 4, [3, 4, 5], [0.0, -6.0, -6.0], [1.0, 6.0, 6.0], 1.0)
+    assert L.dg_rhs_static(ctypes.byref(bad), fake_f, None, fake_out, None) == dg.DG_ERR_INVALID

@@ -1,18 +1,31 @@
 """Full-size checks in the launch configuration the benchmark times.
 
-* 1D2V ring, 32^3 elements, n = 8 (16.8 M DOF) and 1D2V Maxwellian with 8
-  modes, 64 x 48 x 48 elements, n = 9 (107.5 M DOF):
-  - FP32 vs FP64 storage over 10 SSP-RK3 steps from the same state: the
-    relative L2 difference of the states after every step <= 1e-5 (the FP32
-    bound; both runs in the benchmark's launch configuration);
-  - the oracle on a 1/8 x-subdomain: x elements [0, Nx/8) plus one halo
-    element on each side are cut out of the GPU's input state, E comes from
-    the oracle's own full-domain Poisson solve (checked against the GPU's E),
-    and the oracle's FP64 RHS on the interior elements is compared with the
-    GPU's FP64 full-domain RHS there (1e-12 of the size |f| |a| J of its
-    terms, which nearly cancel for these states).  The
-    FP32 RHS is not compared: for these near-equilibrium states the RHS is a
-    small difference of large terms, so FP32 is judged on the state.
+Workloads: 1D2V ring, 32^3 elements, n = 8 (16.8 M DOF), and 1D2V Maxwellian
+with 8 modes, 64 x 48 x 48 elements, n = 9 (107.5 M DOF), both in the padded
+v-row layout (DG_LAYOUT_VPAD) the benchmark uses; at 107.5 M DOF the stage
+kernels store with the non-temporal hint (the three state buffers exceed the
+last-level cache), as they do in FP64 at 16.8 M DOF.
+
+* Random non-equilibrium state (U(0,1) at every node, a random E): the FP32
+  RHS against the FP64 RHS on the whole grid, and against the FP64 oracle on
+  the 1/8 x-subdomain [0, Nx/8) (one halo element each side), relative L2
+  <= 1e-5 (the FP32 bound).  Every axis matters here: the oracle gives the
+  x, u and v terms 0.23, 0.67, 0.67 of the RHS norm (Maxwellian grid) and
+  0.64, 0.51, 0.51 (ring grid), all far above the bar.
+* The workload's own initial state:
+  - E against the oracle's full-domain Poisson solve, and the FP64 RHS
+    against the oracle on the 1/8 x-subdomain (1e-12 of the size |f| |a| J
+    of its terms, which nearly cancel for these states);
+  - FP32 vs FP64 storage over 10 SSP-RK3 steps from the same state, judged on
+    the increments f_k - f_0 (relative to |f_k - f_0|), not on the states,
+    which the equilibrium dominates.  Over 10 steps the oracle puts the
+    increment at 2.1e-5 |f| (Maxwellian) and 5.4e-6 |f| (ring); the x term
+    alone is 0.31 (Maxwellian) and 0.63 (ring) of it, and the u and v terms
+    are each two to three orders of magnitude larger than the increment and
+    cancel each other (gyration of a gyrotropic state).  FP32 storage
+    rounds f to 6e-8 |f| at every stage, i.e. about 3e-3 (Maxwellian) and
+    1e-2 (ring) of the increment per step; the bar, 0.1, stays below the
+    smallest axis share, so an FP32-only error in any axis fails it.
 * The 64-run uneven sweep: four sampled runs of the batch equal their solo
   runs bit for bit after two steps.
 """
@@ -24,7 +37,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import grid, lgl, poisson, rhs  # noqa: E402
-from paper_2202_13532_amd import dg, workloads  # noqa: E402
+from paper_2202_13532_amd import dg, inputs, workloads  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -51,18 +64,60 @@ def _subdomain_rhs(wl, f_full, E_full):
     return r[1:m + 1]
 
 
+def _workload(name):
+    return workloads.ring_1d2v_n8() if name == "ring_1d2v_n8" else workloads.maxwell_1d2v_n9()
+
+
+def _solvers(wl):
+    s32 = dg.Solver(wl.nv, wl.n, wl.nelem, wl.lo, wl.hi, wl.omega_c, 0, "f32", layout="vpad")
+    s64 = dg.Solver(wl.nv, wl.n, wl.nelem, wl.lo, wl.hi, wl.omega_c, 0, "f64", layout="vpad")
+    return s32, s64
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("name", ["ring_1d2v_n8", "maxwell_1d2v_n9"])
+def test_fullsize_fp32_rhs_random_state(name):
+    print("full size, random state", name, flush=True)
+    wl = _workload(name)
+    s32, s64 = _solvers(wl)
+    fh = inputs.random_nodal(s32.dense_shape, 21).astype(np.float32).astype(np.float64)
+    Eh = inputs.random_field(wl.nelem[0] * wl.n, 9)
+    E = torch.from_numpy(Eh).cuda()
+    d32 = torch.from_numpy(fh).float().cuda()
+    r32 = s32.unpack(s32.rhs(s32.pack(d32), E)).cpu().numpy().astype(np.float64)
+    del d32
+    d64 = torch.from_numpy(fh).cuda()
+    r64 = s64.unpack(s64.rhs(s64.pack(d64), E)).cpu().numpy()
+    del d64
+    e_full = _rel_l2(r32, r64)
+    m = wl.nelem[0] // 8
+    ref = _subdomain_rhs(wl, fh, Eh)
+    e_sub = _rel_l2(r32[:m], ref)
+    e64 = float(np.max(np.abs(r64[:m] - ref)) / np.max(np.abs(ref)))
+    print("FP32 vs FP64 RHS %.3e, FP32 vs oracle (1/8 subdomain) %.3e, FP64 vs oracle (max) %.3e"
+          % (e_full, e_sub, e64), flush=True)
+    assert e_full <= 1e-5
+    assert e_sub <= 1e-5
+    assert e64 <= 1e-12
+    s32.close()
+    s64.close()
+
+
 @pytest.mark.parametrize("name", ["ring_1d2v_n8", "maxwell_1d2v_n9"])
 def test_fullsize_fp32_vs_fp64_and_oracle_subdomain(name):
     print("full size", name, flush=True)
-    wl = workloads.ring_1d2v_n8() if name == "ring_1d2v_n8" else workloads.maxwell_1d2v_n9()
-    s32 = dg.Solver(wl.nv, wl.n, wl.nelem, wl.lo, wl.hi, wl.omega_c, 0, "f32")
-    s64 = dg.Solver(wl.nv, wl.n, wl.nelem, wl.lo, wl.hi, wl.omega_c, 0, "f64")
-    f32 = _state(wl, s32, torch.float32)
-    f64 = f32.to(torch.float64).contiguous()
+    wl = _workload(name)
+    s32, s64 = _solvers(wl)
+    d32 = _state(wl, s32, torch.float32)
+    f32 = s32.pack(d32)
+    f64 = s64.pack(d32.double())
     # FP64 RHS and field at the initial state
-    r64 = s64.rhs(f64)
+    r64 = s64.unpack(s64.rhs(f64))
     E64 = s64.poisson(f64)
-    fh = f64.cpu().numpy()
+    fh = d32.double().cpu().numpy()
     gfull = grid.PhaseGrid(2, wl.n, wl.nelem, wl.lo, wl.hi, wl.omega_c)
     nd = rhs.density(gfull, fh)
     Eo, _ = poisson.field_from_density(gfull, nd)
@@ -79,18 +134,24 @@ def test_fullsize_fp32_vs_fp64_and_oracle_subdomain(name):
                                          + vmax * wl.omega_c * 2 / dxs[2])
     print("FP64 RHS vs oracle:", np.max(np.abs(g64 - ref)), "term scale", term, flush=True)
     assert np.max(np.abs(g64 - ref)) <= 1e-12 * term
-    del r64, g64, ref, nd
-    del fh
-    # FP32 vs FP64, every step
+    del r64, g64, ref, nd, fh
+    # FP32 vs FP64: increments from the common initial state, every step
     dt = wl.cfl_fraction * s64.dt_max(max(float(E64.abs().max()), 0.05))
+    f0 = d32.double()
+    del d32
     worst = 0.0
-    for _ in range(10):
+    for k in range(10):
         s32.step(f32, dt, 1)
         s64.step(f64, dt, 1)
-        diff = float(torch.linalg.vector_norm(f32.double() - f64) / torch.linalg.vector_norm(f64))
+        inc64 = s64.unpack(f64) - f0
+        inc32 = s32.unpack(f32).double() - f0
+        diff = float(torch.linalg.vector_norm(inc32 - inc64) / torch.linalg.vector_norm(inc64))
+        print("step %d: |f_k - f_0| / |f_0| = %.3e, FP32 vs FP64 increment %.3e"
+              % (k + 1, float(torch.linalg.vector_norm(inc64) / torch.linalg.vector_norm(f0)), diff), flush=True)
         worst = max(worst, diff)
-    print("FP32 vs FP64, worst step over 10:", worst, flush=True)
-    assert worst < 1e-5
+        del inc64, inc32
+    print("FP32 vs FP64 increments, worst step over 10:", worst, flush=True)
+    assert worst < 0.1
     s32.close()
     s64.close()
 

@@ -54,7 +54,7 @@ typedef struct dg_ctx dg_ctx;
 typedef enum {
   DG_OK = 0,
   DG_ERR_INVALID = 1,     /* bad argument or configuration                     */
-  DG_ERR_UNSUPPORTED = 2, /* valid in principle, not built (e.g. n outside 2..9) */
+  DG_ERR_UNSUPPORTED = 2, /* valid in principle, not built (e.g. n outside 2..12) */
   DG_ERR_OOM = 3,         /* workspace smaller than dg_workspace_bytes()        */
   DG_ERR_DEVICE = 4,      /* HIP runtime error                                  */
   DG_ERR_CFL = 5,         /* dt above dg_dt_max()                               */
@@ -85,7 +85,7 @@ typedef enum { DG_LAYOUT_DENSE = 0, DG_LAYOUT_VPAD = 1 } dg_layout;
 
 typedef struct {
   int32_t nv;        /* velocity dimensions: 1 (1D1V) or 2 (1D2V)               */
-  int32_t n;         /* LGL nodes per element per axis, 2..9                     */
+  int32_t n;         /* LGL nodes per element per axis, 2..12                    */
   int32_t nelem[3];  /* elements along x, u (v for 1D1V), v; nelem[2] unused if nv==1 */
   double lo[3];      /* axis lower bounds                                         */
   double hi[3];      /* axis upper bounds (x period L = hi[0] - lo[0])            */
@@ -166,12 +166,18 @@ dg_status dg_rk_step(dg_ctx* ctx, void* f, double dt, int32_t nsteps, dg_diag* h
  * kernels that follow it.  Same CFL and finiteness checks as dg_rk_step.   */
 dg_status dg_profile_step(dg_ctx* ctx, void* f, double dt, int32_t nsteps, double* host_ms);
 
-/* Full diagnostics of state f (its own Poisson solve) into *host_out; waits. */
+/* Full diagnostics of state f (its own Poisson solve) into *host_out; waits.
+ * The quantities are those the paper tracks over its runs (Sec. 6, energy
+ * figure): mass, the domain-integrated field energy (the paper leaves its
+ * definition open; taken as 1/2 int E^2 dx by nodal LGL quadrature), kinetic
+ * energy and the L2 norm of f, with max |E|.                                */
 dg_status dg_diagnostics(dg_ctx* ctx, const void* f, dg_diag* host_out);
 
 /* Largest stable SSP-RK3 step for a field bounded by max_abs_E:
  * C_n / sum_axes(max|speed_a| / dx_a), C_n the RK3 + upwind-DG stability
- * limit from the Bloch eigenvalues of the 1-D operator.  Host-only.         */
+ * limit from the Bloch eigenvalues of the 1-D operator (the paper defers its
+ * CFL numbers to the DG literature, Sec. 6; this is the exact limit of the
+ * scheme as implemented).  Host-only.                                       */
 double dg_dt_max(const dg_ctx* ctx, double max_abs_E);
 
 /* Node coordinates of one axis (0 = x, 1 = u or v, 2 = v): nelem*n doubles

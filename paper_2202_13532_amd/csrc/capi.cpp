@@ -494,7 +494,7 @@ const char* check_cfg(const dg_config* cfg, dg_status* st) {
   *st = DG_ERR_INVALID;
   if (const char* why = validate(cfg)) return why;
   *st = DG_ERR_UNSUPPORTED;
-  if (cfg->n > dgk::kMaxN) return "n above 9 is not built";
+  if (cfg->n > dgk::kMaxN) return "n above 12 is not built";
   const Layout L = make_layout(cfg);
   if (L.ntiles <= 0 || static_cast<long long>(L.Nx) * L.ntiles_slab > 0x7fffffffLL) return "grid too large";
   // one x element must be addressable by a 31-bit buffer offset

@@ -7,7 +7,7 @@
 namespace dgk {
 
 constexpr int kWave = 64;
-constexpr int kMaxN = 9;
+constexpr int kMaxN = 12;
 constexpr int kRing = 1024;   // diagnostics records per device ring
 
 // v-elements covered by one wave for n nodes: the wave's lanes hold the

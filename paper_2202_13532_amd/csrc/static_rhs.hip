@@ -131,7 +131,7 @@ hipError_t launch_tables(int n, const TableArgs& a, long long threads, hipStream
 #define DG_TAB_CASE(NN) \
   case NN: hipLaunchKernelGGL(tables_kernel<NN>, dim3(grid), dim3(256), 0, s, a); break;
     DG_TAB_CASE(2) DG_TAB_CASE(3) DG_TAB_CASE(4) DG_TAB_CASE(5) DG_TAB_CASE(6) DG_TAB_CASE(7) DG_TAB_CASE(8)
-    DG_TAB_CASE(9)
+    DG_TAB_CASE(9) DG_TAB_CASE(10) DG_TAB_CASE(11) DG_TAB_CASE(12)
 #undef DG_TAB_CASE
     default: return hipErrorInvalidValue;
   }

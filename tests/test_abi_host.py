@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
     assert set(dg.EXPORTED) <= set(names)
 
 
-@pytest.mark.parametrize("n", range(2, 10))
+@pytest.mark.parametrize("n", range(2, 13))
 def test_host_basis_matches_oracle(n):
     _lib()
     b = dg.dg_basis(n)
@@ -58,7 +58,7 @@ def test_host_connection_tensor_matches_oracle_quadrature(n, N, L, pmax):
     assert np.max(np.abs(T - To[pmax + 1:])) < 1e-15
 
 
-@pytest.mark.parametrize("n", range(2, 10))
+@pytest.mark.parametrize("n", range(2, 13))
 def test_host_courant_number_matches_oracle(n):
     _lib()
     assert abs(dg.dg_courant_number(n) / cfl.courant_number(n) - 1) < 2e-5
@@ -76,7 +76,7 @@ def test_workspace_bytes_and_config_validation():
            dg.make_config(1, 4, [0, 4], [0, 0], [1, 1]),
            dg.make_config(1, 4, [4, 4], [0, 1], [1, 1]),
            dg.make_config(1, 4, [4, 4], [0, 0], [1, 1], omega_c=1.0),
-           dg.make_config(2, 10, [4, 4, 4], [0, 0, 0], [1, 1, 1])]
+           dg.make_config(2, 13, [4, 4, 4], [0, 0, 0], [1, 1, 1])]
     for c in bad:
         assert dg.dg_workspace_bytes(c) == 0
 
@@ -114,8 +114,8 @@ def test_init_rejects_bad_arguments_before_touching_a_device():
     assert st == dg.DG_ERR_OOM
     st = dg.lib().dg_init(ctypes.byref(good), None, 1 << 30, None, ctypes.byref(ctx))
     assert st == dg.DG_ERR_INVALID
-    n10 = dg.make_config(1, 10, [4, 4], [0, -1], [1, 1])
-    st = dg.lib().dg_init(ctypes.byref(n10), ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(ctx))
+    n13 = dg.make_config(1, 13, [4, 4], [0, -1], [1, 1])
+    st = dg.lib().dg_init(ctypes.byref(n13), ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(ctx))
     assert st == dg.DG_ERR_UNSUPPORTED
     # entry points on a NULL context fail cleanly
     assert dg.lib().dg_rhs(None, None, None, None) == dg.DG_ERR_INVALID

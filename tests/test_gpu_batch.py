@@ -19,6 +19,8 @@ SMALL = [
     (2, 5, [2, 3, 13], [0.0, -6.0, -6.0], [5.0, 6.0, 6.0], 0.5),
     (2, 9, [2, 2, 8], [0.0, -8.0, -8.0], [20.0, 8.0, 8.0], 0.0),
     (1, 2, [4, 70], [0.0, -4.0], [3.0, 4.0], 0.0),
+    (2, 11, [2, 2, 6], [0.0, -6.0, -6.0], [6.0, 6.0, 6.0], 1.0),
+    (1, 12, [2, 9], [0.0, -5.0], [4.0, 5.0], 0.0),
 ]
 
 

@@ -28,6 +28,9 @@ CASES = [
     (5, [1, 2, 13], [0.0, -3.0, -3.0], [1.0, 3.0, 3.0], 2.0, "periodic"),
     (6, [2, 3, 11], [0.0, -5.0, -4.0], [4.0, 5.0, 4.0], -1.3, "periodic"),
     (7, [2, 2, 4], [0.0, -4.0, -4.0], [4.0, 4.0, 4.0], 0.0, "periodic"),
+    (10, [2, 2, 13], [0.0, -6.0, -6.0], [5.0, 6.0, 6.0], 1.0, "periodic"),
+    (11, [2, 3, 7], [0.0, -5.0, -5.0], [4.0, 5.0, 5.0], -0.9, "zero_inflow"),
+    (12, [1, 2, 11], [0.0, -6.0, -6.0], [3.0, 6.0, 6.0], 1.0, "periodic"),
 ]
 
 

@@ -57,6 +57,12 @@ RHS_CASES = [
     (2, 6, [2, 3, 11], [0.0, -5.0, -4.0], [4.0, 5.0, 4.0], -1.3, "periodic"),
     (2, 7, [2, 2, 4], [0.0, -4.0, -4.0], [4.0, 4.0, 4.0], 0.0, "periodic"),
     (2, 2, [4, 3, 40], [0.0, -4.0, -4.0], [4.0, 4.0, 4.0], 1.0, "periodic"),
+    # n = 10..12 (one to five v elements per 64-lane chunk, ragged tails)
+    (1, 10, [3, 13], [0.0, -6.0], [5.0, 6.0], 0.0, "periodic"),
+    (1, 12, [2, 11], [0.0, -4.0], [3.0, 4.0], 0.0, "zero_inflow"),
+    (2, 10, [2, 3, 13], [0.0, -6.0, -5.0], [6.0, 6.0, 5.0], 1.0, "periodic"),
+    (2, 11, [2, 2, 12], [0.0, -5.0, -5.0], [4.0, 5.0, 5.0], -0.6, "zero_inflow"),
+    (2, 12, [2, 3, 7], [0.0, -6.0, -6.0], [8.0, 6.0, 6.0], 1.0, "periodic"),
 ]
 
 
@@ -118,8 +124,11 @@ def _initial(g, nv, k):
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("case", [_landau_1d1v(), _landau_1d1v(7, (5, 11)), _ring_1d2v(8, (4, 6, 12)),
-                                  _ring_1d2v(9, (3, 5, 9)), _ring_1d2v(4, (6, 10, 18))],
-                         ids=["landau_n4", "landau_n7", "ring_n8", "ring_n9", "ring_n4"])
+                                  _ring_1d2v(9, (3, 5, 9)), _ring_1d2v(4, (6, 10, 18)),
+                                  _landau_1d1v(12, (3, 8)), _ring_1d2v(10, (3, 4, 7)),
+                                  _ring_1d2v(11, (2, 4, 6)), _ring_1d2v(12, (2, 3, 6))],
+                         ids=["landau_n4", "landau_n7", "ring_n8", "ring_n9", "ring_n4", "landau_n12", "ring_n10",
+                              "ring_n11", "ring_n12"])
 def test_one_step_parity(case, storage):
     nv, n, nelem, lo, hi, wc = case
     print("step parity", case, storage, flush=True)

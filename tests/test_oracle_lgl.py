@@ -70,7 +70,7 @@ def _brute_integrals(n):
     return M, S
 
 
-@pytest.mark.parametrize("n", range(2, 11))
+@pytest.mark.parametrize("n", range(2, 13))
 def test_operators_against_quadrature(n):
     o = lgl.operators(n)
     M, S = _brute_integrals(n)
@@ -82,7 +82,7 @@ def test_operators_against_quadrature(n):
     assert np.allclose(o["Xi"][:, 1], Minv_b[:, -1], atol=1e-9 * n * n)
 
 
-@pytest.mark.parametrize("n", range(2, 11))
+@pytest.mark.parametrize("n", range(2, 13))
 def test_paper_closed_forms(n):
     """M^-1 S agrees with eq. num_flux_wow, eq. internal_flux_wow, eq. derivative."""
     o = lgl.operators(n)
@@ -111,7 +111,7 @@ def test_paper_closed_forms(n):
     assert np.allclose(M @ o["Minv"], np.eye(n), atol=1e-11)
 
 
-@pytest.mark.parametrize("n", range(2, 11))
+@pytest.mark.parametrize("n", range(2, 13))
 def test_summation_by_parts_and_mass_row(n):
     o = lgl.operators(n)
     B = np.zeros((n, n)); B[0, 0] = -1; B[-1, -1] = 1

@@ -8,7 +8,8 @@ from oracle import brute, cfl, grid, lgl, rhs, rk
 
 
 @pytest.mark.parametrize("n,ne,vbc", [(2, (3, 3), "periodic"), (3, (3, 4), "periodic"),
-                                      (4, (2, 3), "zero_inflow"), (3, (3, 3), "zero_inflow")])
+                                      (4, (2, 3), "zero_inflow"), (3, (3, 3), "zero_inflow"),
+                                      (10, (2, 2), "periodic"), (12, (2, 2), "zero_inflow")])
 def test_rhs_matches_brute_force_1d1v(n, ne, vbc):
     rng = np.random.default_rng(10 * n + ne[0])
     g = grid.PhaseGrid(1, n, list(ne), [0.0, -2.0], [2 * math.pi, 2.5], vbc=vbc)

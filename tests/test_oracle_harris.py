@@ -84,3 +84,22 @@ def test_eigenmode_is_an_eigenfunction_of_the_oracle_rhs(mode):
     d = (rk.L(g, ops, f0 + eps * f1) - rk.L(g, ops, f0)) / eps
     expect = (-1j * w * B * psi).real
     assert np.linalg.norm(d - expect) < 0.03 * np.linalg.norm(expect)
+
+
+@pytest.mark.parametrize("which", ["A", "B"])
+def test_case_study_density_amplitude_of_the_mode(which):
+    """The closed form (Jacobi-Anger) of the mode's density used to scale the
+    case-study perturbation equals brute-force quadrature of eq. ic over the
+    velocity plane; the ring's thermal energy is App. B's exact moment."""
+    from paper_2202_13532_amd import case_study as cs
+    kx, k0, _, hi = cs.geometry(which)
+    om = cs.CASES[which]["omega"]
+    h = 0.03
+    g = np.arange(-12 + h / 2, 12, h)
+    psi = inputs.cyclotron_mode(0.0, g[:, None], g[None, :], kx, k0, om, 6, complex_out=True)
+    brute = psi.sum() * h * h
+    assert abs(cs.mode_density(k0, om) - brute) < 1e-10 * abs(brute)
+    # App. B: alpha^2 (j + 1 - (Gamma(j + 3/2) / Gamma(j + 1))^2), close to 1/4 for large j
+    per_length = cs.thermal_energy(which) / hi[0]
+    assert abs(per_length - (7.0 - (special.gamma(7.5) / special.gamma(7.0)) ** 2)) < 1e-12
+    assert abs(per_length / paper_value("ring_thermal_energy_per_length")["value"] - 1.0) < 0.03

@@ -166,6 +166,23 @@ dg_status dg_rk_step(dg_ctx* ctx, void* f, double dt, int32_t nsteps, dg_diag* h
  * kernels that follow it.  Same CFL and finiteness checks as dg_rk_step.   */
 dg_status dg_profile_step(dg_ctx* ctx, void* f, double dt, int32_t nsteps, double* host_ms);
 
+/* delta-f storage (Sec. 2: the weak form is linear in f for a given field, so
+ * L(f0 + g) = L(f0) + L(g)).  f0_host: an x-uniform background f0(u, v) as
+ * host FP64 nodal values, dense [Nu*n][Nv*n] (1D2V) or [Nv*n] (1D1V), which
+ * must be continuous across every velocity element face including the
+ * periodic wrap (relative jump <= 1e-10; then its upwind face values do not
+ * depend on the direction and L(f0) = -E(x) G_u(u, v) + G_b(u, v) exactly,
+ * with G_u its weak u derivative and G_b its gyration -vB G_u + uB G_v, both
+ * built once in FP64 on the host).  Afterwards every state the context is
+ * given holds g = f - f0: dg_rhs returns L(f0 + g), dg_rk_step advances g,
+ * dg_poisson and the diagnostics (mass, energies, L2 norm) are those of
+ * f0 + g.  With FP32 storage this keeps the rounding of f0 out of every
+ * stage.  NULL returns to whole-f states.  Needs periodic velocity
+ * boundaries (DG_ERR_UNSUPPORTED otherwise); invalidates the cached step
+ * graph; waits.  The learned-correction calls reject contexts with a
+ * background.                                                               */
+dg_status dg_set_background(dg_ctx* ctx, const double* f0_host);
+
 /* Full diagnostics of state f (its own Poisson solve) into *host_out; waits.
  * The quantities are those the paper tracks over its runs (Sec. 6, energy
  * figure): mass, the domain-integrated field energy (the paper leaves its

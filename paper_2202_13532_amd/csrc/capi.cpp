@@ -94,6 +94,12 @@ Layout make_layout(const dg_config* c, bool stage_buffers = true) {
   L.off_vc = take(static_cast<size_t>(L.Nv) * L.n * L.esize);
   L.off_uc64 = take(static_cast<size_t>(L.Nu) * L.n * 8);
   L.off_vc64 = take(static_cast<size_t>(L.Nv) * L.n * 8);
+  // background tables (dg_set_background): G_u and G_b in the state-row
+  // layout (1D2V) or G_v (1D1V) in the storage precision, f0 in FP64
+  const size_t vrows = c->nv == 2 ? static_cast<size_t>(L.Nu) * L.n : 1;
+  L.off_bgu = take(stage_buffers ? vrows * L.lpitch * L.esize : 0);
+  L.off_bgb = take(stage_buffers && c->nv == 2 ? vrows * L.lpitch * L.esize : 0);
+  L.off_bg64 = take(stage_buffers ? vrows * L.Nv * L.n * 8 : 0);
   L.total = o;
   return L;
 }
@@ -174,6 +180,11 @@ void fill_pack(const dg_ctx* c, dgk::StageArgs<T>* p, const void* fin, const voi
   a.uc64 = c->at<const double>(L.off_uc64);
   a.vc64 = c->at<const double>(L.off_vc64);
   a.partials = partials;
+  if (c->bg) {
+    a.bg_u = c->at<const T>(L.off_bgu);
+    a.bg_b = c->cfg.nv == 2 ? c->at<const T>(L.off_bgb) : nullptr;
+    a.bg64 = c->at<const double>(L.off_bg64);
+  }
   a.hu = c->cfg.nv == 2 ? 0.5 * c->dx[1] : 1.0;
   a.Nx = L.Nx;
   a.Nu = L.Nu;
@@ -270,6 +281,7 @@ void fill_field(const dg_ctx* c, dgk::FieldArgs* pa, double* E, double* coeffs, 
   a.last = c->at<double>(L.off_last);
   a.counter = c->at<int>(L.off_ctr);
   a.record = record ? 1 : 0;
+  a.mass0 = c->bg ? c->mass0 : 0.0;
 }
 
 dg_status field(dg_ctx* c, double* E, double* coeffs, bool record) {
@@ -709,6 +721,107 @@ dg_status dg_diagnostics(dg_ctx* ctx, const void* f, dg_diag* host_out) {
   host_out->step = 0;
   DG_TRY(leave(ctx));
   return host_out->finite ? DG_OK : fail(ctx, DG_ERR_NONFINITE, "dg_diagnostics: non-finite moments");
+}
+
+dg_status dg_set_background(dg_ctx* ctx, const double* f0) {
+  if (!ctx) return DG_ERR_INVALID;
+  // a cached step graph holds the stage kernels of the previous mode
+  if (ctx->gexec) {
+    (void)hipGraphExecDestroy(ctx->gexec);
+    ctx->gexec = nullptr;
+  }
+  if (!f0) {
+    ctx->bg = false;
+    ctx->mass0 = 0.0;
+    return DG_OK;
+  }
+  ctx->bg = false;
+  const dg_config& C = ctx->cfg;
+  if (C.vbc != DG_VBC_PERIODIC) return fail(ctx, DG_ERR_UNSUPPORTED, "dg_set_background: needs periodic velocity boundaries");
+  const Layout& L = ctx->L;
+  const dgh::Basis& b = ctx->basis;
+  const int n = L.n;
+  const bool two = C.nv == 2;
+  const int nu = two ? L.Nu * n : 1, nvn = L.Nv * n;
+  auto F = [&](int p, int q) { return f0[static_cast<size_t>(p) * nvn + q]; };
+  double fmax = 0.0;
+  for (size_t i = 0; i < static_cast<size_t>(nu) * nvn; ++i) {
+    if (!std::isfinite(f0[i])) return fail(ctx, DG_ERR_INVALID, "dg_set_background: f0 is not finite");
+    fmax = std::max(fmax, std::fabs(f0[i]));
+  }
+  // continuity across every element face of both velocity axes (periodic
+  // wrap included): then the upwind face value of f0 is the same from either
+  // side and L(f0) is linear in E without a sign choice
+  const double tol = 1e-10 * fmax;
+  for (int p = 0; p < nu; ++p)
+    for (int e = 0; e < L.Nv; ++e)
+      if (std::fabs(F(p, e * n + n - 1) - F(p, ((e + 1) % L.Nv) * n)) > tol)
+        return fail(ctx, DG_ERR_INVALID, "dg_set_background: f0 jumps across a v face");
+  if (two)
+    for (int q = 0; q < nvn; ++q)
+      for (int e = 0; e < L.Nu; ++e)
+        if (std::fabs(F(e * n + n - 1, q) - F(((e + 1) % L.Nu) * n, q)) > tol)
+          return fail(ctx, DG_ERR_INVALID, "dg_set_background: f0 jumps across a u face");
+  // G = J (Upsilon f0 + Xi_0 f0(left face) - Xi_1 f0(right face)) along an axis
+  auto deriv = [&](int Ne, double J, auto get, auto put) {
+    for (int e = 0; e < Ne; ++e)
+      for (int j = 0; j < n; ++j) {
+        double s = b.xi_face[j * 2 + 0] * get(e * n) - b.xi_face[j * 2 + 1] * get(e * n + n - 1);
+        for (int k = 0; k < n; ++k) s += b.ups[j * n + k] * get(e * n + k);
+        put(e * n + j, J * s);
+      }
+  };
+  const int vax = two ? 2 : 1;
+  std::vector<double> Gv(static_cast<size_t>(nu) * nvn), Gu(two ? static_cast<size_t>(nu) * nvn : 0);
+  for (int p = 0; p < nu; ++p)
+    deriv(L.Nv, 2.0 / ctx->dx[vax], [&](int q) { return F(p, q); },
+          [&](int q, double g) { Gv[static_cast<size_t>(p) * nvn + q] = g; });
+  if (two)
+    for (int q = 0; q < nvn; ++q)
+      deriv(L.Nu, 2.0 / ctx->dx[1], [&](int p) { return F(p, q); },
+            [&](int p, double g) { Gu[static_cast<size_t>(p) * nvn + q] = g; });
+  // tables in the storage precision: 1D2V G_u and G_b = -v B G_u + u B G_v
+  // (the gyration of f0, cancelled in FP64) in the state's row layout;
+  // 1D1V G_v (the whole L(f0) is -E G_v)
+  const std::vector<double> uc = two ? axis_nodes(b, L.Nu, C.lo[1], C.hi[1]) : std::vector<double>(1, 0.0);
+  const std::vector<double> vc = axis_nodes(b, L.Nv, C.lo[vax], C.hi[vax]);
+  const int tv = dgk::tv_of(n);
+  const size_t rowlen = two ? static_cast<size_t>(L.lpitch) : static_cast<size_t>(nvn);
+  std::vector<double> tu(static_cast<size_t>(nu) * rowlen, 0.0), tb(two ? tu.size() : 0, 0.0);
+  for (int p = 0; p < nu; ++p)
+    for (int q = 0; q < nvn; ++q) {
+      const int iv = q / n, c = iv / tv;
+      const size_t pos = two ? static_cast<size_t>(c) * L.cpitch + (iv - c * tv) * n + q % n : q;
+      const size_t i = static_cast<size_t>(p) * nvn + q;
+      if (two) {
+        tu[p * rowlen + pos] = Gu[i];
+        tb[p * rowlen + pos] = -vc[q] * C.omega_c * Gu[i] + uc[p] * C.omega_c * Gv[i];
+      } else {
+        tu[pos] = Gv[i];
+      }
+    }
+  // mass of f0 over the whole domain
+  const std::vector<double> wu = two ? axis_weights(b, L.Nu, C.lo[1], C.hi[1]) : std::vector<double>(1, 1.0);
+  const std::vector<double> wv = axis_weights(b, L.Nv, C.lo[vax], C.hi[vax]);
+  double m0 = 0.0;
+  for (int p = 0; p < nu; ++p)
+    for (int q = 0; q < nvn; ++q) m0 += wu[p] * wv[q] * F(p, q);
+  m0 *= C.hi[0] - C.lo[0];
+  auto upload = [&](size_t off, const std::vector<double>& v) -> hipError_t {
+    if (ctx->f64()) return hipMemcpyAsync(ctx->ws + off, v.data(), v.size() * 8, hipMemcpyHostToDevice, ctx->stream);
+    std::vector<float> w(v.begin(), v.end());
+    hipError_t e = hipMemcpyAsync(ctx->ws + off, w.data(), w.size() * 4, hipMemcpyHostToDevice, ctx->stream);
+    return e == hipSuccess ? hipStreamSynchronize(ctx->stream) : e;   // w is released on return
+  };
+  DG_TRY(enter(ctx));
+  DG_HIP(ctx, upload(L.off_bgu, tu));
+  if (two) DG_HIP(ctx, upload(L.off_bgb, tb));
+  DG_HIP(ctx, hipMemcpyAsync(ctx->ws + L.off_bg64, f0, static_cast<size_t>(nu) * nvn * 8, hipMemcpyHostToDevice, ctx->stream));
+  DG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  DG_TRY(leave(ctx));
+  ctx->bg = true;
+  ctx->mass0 = m0;
+  return DG_OK;
 }
 
 dg_status dg_node_coords(const dg_ctx* ctx, int32_t axis, double* host_out) {

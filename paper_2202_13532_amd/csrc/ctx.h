@@ -20,7 +20,8 @@ struct Layout {
   int cpitch = 0, lpitch = 0;   // values per v chunk and per row of a state array (dg_layout)
   size_t selems = 0;            // values in a state array
   size_t off_B, off_C, off_part, off_mom, off_dens, off_E, off_cpart, off_mpart, off_coef, off_ring,
-      off_last, off_ctr, off_T, off_z1, off_wx, off_wu, off_wv, off_uc, off_vc, off_uc64, off_vc64, total;
+      off_last, off_ctr, off_T, off_z1, off_wx, off_wu, off_wv, off_uc, off_vc, off_uc64, off_vc64,
+      off_bgu, off_bgb, off_bg64, total;
 };
 
 }  // namespace dgi
@@ -44,6 +45,9 @@ struct dg_ctx {
   const void* g_f = nullptr;
   double g_dt = 0.0;
   bool g_diag = false;
+  // background f0 (dg_set_background): states hold g = f - f0
+  bool bg = false;
+  double mass0 = 0.0;
 
   template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
   bool f64() const { return cfg.storage == DG_F64; }

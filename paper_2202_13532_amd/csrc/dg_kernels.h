@@ -28,6 +28,9 @@ struct StageArgs {
   const double* uc64;     // Nu*n u-node coordinates in FP64 (moments only)
   const double* vc64;     // Nv*n v-node coordinates in FP64 (moments only)
   double* partials;       // density partials or nullptr
+  const T* bg_u;          // background tables (state-row layout, storage precision) or nullptr:
+  const T* bg_b;          //   1D2V G_u, G_b of L(f0) = -E G_u + G_b; 1D1V bg_u = G_v (Nv*n)
+  const double* bg64;     // background f0 (FP64, dense [Nu*n][Nv*n] or [Nv*n]) for the moments, or nullptr
   double hu;              // du/2 (u-axis Jacobian inverse), nv = 2
   int Nx, Nu, Nv, nvchunks;
   int cpitch, lpitch;     // values per v chunk / per (x node, u node) row of the arrays
@@ -55,6 +58,7 @@ struct FieldArgs {
   double* last;            // always receives the newest record (8 doubles)
   int* counter;            // ring write counter
   int record;              // 1: append a record
+  double mass0;            // mass of the background f0 (added to the recorded mass)
 };
 
 // Launchers return hipSuccess or the launch error.  `args` points to a

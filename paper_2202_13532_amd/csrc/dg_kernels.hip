@@ -224,7 +224,10 @@ constexpr int lds_words_1v() { return (N + 1) * lds_row<N>(); }
 // lds: lds_words_2v<N>() words (input rows + 2 result buffers; row N of each
 // is the scratch row of idle lanes); hbuf: N*N words; dsum: dens_words<T, N>()
 // doubles.
-template <typename T, int N, bool UN>
+// BG: the state holds g = f - f0 for an x-uniform background f0(u, v)
+// (dg_set_background); the RHS then adds L(f0) = -E(x) G_u(u, v) + G_b(u, v),
+// two FP64-built tables in the state's row layout.
+template <typename T, int N, bool UN, bool BG = false>
 __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* lds, T* hbuf, double* dsum) {
   using B = Buf<T>;
   constexpr unsigned S = sizeof(T);
@@ -377,6 +380,19 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   const double wvl = act ? a.wv[c0 + lane] * a.hu : 0.0;    // v weight times du/2
   const int ntiles = a.Nu * a.nvchunks;
 
+  // background rows G_u, G_b of this (u element, v chunk): the same for every x node
+  T bgu[BG ? N : 1], bgb[BG ? N : 1];
+  if constexpr (BG) {
+    const unsigned tb = static_cast<unsigned>(a.Nu) * N * LP * S;
+    const auto rgu = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(a.bg_u), 0, static_cast<int>(tb), kRsrcWord3);
+    const auto rgb = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(a.bg_b), 0, static_cast<int>(tb), kRsrcWord3);
+    const unsigned vb = vo + (iu * N * LP + m0) * S;
+#pragma unroll
+    for (int ju = 0; ju < N; ++ju) {
+      bgu[ju] = B::ld(rgu, vb, ju * rowb);
+      bgb[ju] = B::ld(rgb, vb, ju * rowb);
+    }
+  }
   // rows of u^n and of the u face are fetched one row ahead of their use
   T unr[N];
   if (UN) {
@@ -403,9 +419,11 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   // stage combination, store and FP64 density partial of a finished row
   auto finish_row = [&](int jx, const T* acc, const T* lo) {
     T vout[N];
+    const T mE = BG ? -static_cast<T>(a.E[ix * N + jx]) : T(0);
 #pragma unroll
     for (int ju = 0; ju < N; ++ju) {
-      const T rhs = acc[ju] + lo[ju * ROW + 1 + lane];
+      T rhs = acc[ju] + lo[ju * ROW + 1 + lane];
+      if constexpr (BG) rhs += fmadd(mE, bgu[ju], bgb[ju]);
       // with u^n: f + c_un (u^n - f) = c_un u^n + (1 - c_un) f; a nearly
       // steady state then stays bit-identical instead of picking up the same
       // rounding every step (a mass drift in FP32)
@@ -527,20 +545,20 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
 template <typename T, int N>
 constexpr int stage_min_waves() { return sizeof(T) == 8 && N >= 9 && N <= 11 ? 1 : 2; }
 
-template <typename T, int N, bool UN>
+template <typename T, int N, bool UN, bool BG>
 __global__ void __launch_bounds__(kWave, (stage_min_waves<T, N>())) stage2v_kernel(StageArgs<T> a) {
   __shared__ T lds[lds_words_2v<N>()];
   __shared__ T hbuf[N * N];
   __shared__ double dsum[dens_words<T, N>()];
   // reversed order: the tiles the previous stage wrote last are read first
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  stage2v_tile<T, N, UN>(a, a.reverse ? static_cast<int>(gridDim.x) - 1 - b : b, lds, hbuf, dsum);
+  stage2v_tile<T, N, UN, BG>(a, a.reverse ? static_cast<int>(gridDim.x) - 1 - b : b, lds, hbuf, dsum);
 }
 
 // -------------------------------------------------------------------------
 // 1D1V stage kernel.  state [Nx, N, Nv, N]; x speed v, v speed -E(x).
 // -------------------------------------------------------------------------
-template <typename T, int N, bool UN>
+template <typename T, int N, bool UN, bool BG = false>
 __device__ __forceinline__ void stage1v_tile(const StageArgs<T> a, int bid, T* lds) {
   using B = Buf<T>;
   constexpr unsigned S = sizeof(T);
@@ -623,9 +641,12 @@ __device__ __forceinline__ void stage1v_tile(const StageArgs<T> a, int bid, T* l
   const auto ru = xelem_rsrc(a.fun, xstride, ix, xbytes);
   const auto ro = xelem_rsrc(a.out, xstride, ix, xbytes);
   const double wvl = act ? a.wv[c0 + lane] : 0.0;
+  // background (1D1V): L(f0) = -E(x) G_v(v)
+  const T bgv = BG ? a.bg_u[act ? c0 + lane : 0u] : T(0);
 #pragma unroll
   for (int jx = 0; jx < N; ++jx) {
-    const T rhs = acc[jx] + lds[jx * ROW + 1 + lane];
+    T rhs = acc[jx] + lds[jx * ROW + 1 + lane];
+    if constexpr (BG) rhs = fmadd(-static_cast<T>(a.E[ix * N + jx]), bgv, rhs);
     const T base = UN ? fmadd(a.c_un, B::ld(ru, vo, soff(jx)) - f[jx], f[jx]) : a.c_in * f[jx];
     const T v = fmadd(a.c_dt, rhs, base);
     if (a.nt_store) B::st_nt(v, ro, vo, soff(jx));
@@ -637,10 +658,10 @@ __device__ __forceinline__ void stage1v_tile(const StageArgs<T> a, int bid, T* l
   }
 }
 
-template <typename T, int N, bool UN>
+template <typename T, int N, bool UN, bool BG>
 __global__ void __launch_bounds__(kWave) stage1v_kernel(StageArgs<T> a) {
   __shared__ T lds[lds_words_1v<N>()];
-  stage1v_tile<T, N, UN>(a, xcd_remap(blockIdx.x, gridDim.x), lds);
+  stage1v_tile<T, N, UN, BG>(a, xcd_remap(blockIdx.x, gridDim.x), lds);
 }
 
 // -------------------------------------------------------------------------
@@ -734,7 +755,8 @@ __global__ void __launch_bounds__(kWave) moments_kernel(StageArgs<T> a, double* 
       const size_t r = NV == 2
           ? ((static_cast<size_t>(ix) * N + jx) * NUn + static_cast<size_t>(iu) * N + ju) * LP
           : (static_cast<size_t>(ix) * N + jx) * LP;
-      const double fv = act ? static_cast<double>(fin[r]) : 0.0;
+      double fv = act ? static_cast<double>(fin[r]) : 0.0;
+      if (a.bg64 && act) fv += a.bg64[static_cast<size_t>(NV == 2 ? iu * N + ju : 0) * (a.Nv * N) + iv0 * N + jl];
       const double wuv = NV == 2 ? a.wu[iu * N + ju] : 1.0;
       const double u = NV == 2 ? a.uc64[iu * N + ju] : 0.0;
       const double W = wxv * wuv * wvl;
@@ -924,7 +946,7 @@ __device__ __forceinline__ void fieldB_body(const FieldArgs& a) {
       fsum += wred[0][w];
       fmx = fmax(fmx, wred[1][w]);
     }
-    const double m = mass_sh;
+    const double m = mass_sh + a.mass0;
     const double fen = 0.5 * fsum;
     const bool fin = isfinite(m) && isfinite(fen) && isfinite(fmx);
     const int k = (a.record && a.ring) ? *a.counter : -1;
@@ -1024,17 +1046,23 @@ __global__ void __launch_bounds__(kFieldB) fieldB_batched_kernel(const FieldArgs
 // -------------------------------------------------------------------------
 // Host launchers.
 // -------------------------------------------------------------------------
+template <typename T, int N, bool BG>
+static void stage_bg(int nv, bool un, const StageArgs<T>& a, int ntiles, hipStream_t s) {
+  if (nv == 2) {
+    if (un) hipLaunchKernelGGL((stage2v_kernel<T, N, true, BG>), dim3(ntiles), dim3(kWave), 0, s, a);
+    else hipLaunchKernelGGL((stage2v_kernel<T, N, false, BG>), dim3(ntiles), dim3(kWave), 0, s, a);
+  } else {
+    if (un) hipLaunchKernelGGL((stage1v_kernel<T, N, true, BG>), dim3(ntiles), dim3(kWave), 0, s, a);
+    else hipLaunchKernelGGL((stage1v_kernel<T, N, false, BG>), dim3(ntiles), dim3(kWave), 0, s, a);
+  }
+}
+
 template <typename T, int N>
 static hipError_t stage_t(int nv, const void* args, int ntiles, hipStream_t s) {
   const StageArgs<T>& a = *static_cast<const StageArgs<T>*>(args);
   const bool un = a.c_un != T(0);
-  if (nv == 2) {
-    if (un) hipLaunchKernelGGL((stage2v_kernel<T, N, true>), dim3(ntiles), dim3(kWave), 0, s, a);
-    else hipLaunchKernelGGL((stage2v_kernel<T, N, false>), dim3(ntiles), dim3(kWave), 0, s, a);
-  } else {
-    if (un) hipLaunchKernelGGL((stage1v_kernel<T, N, true>), dim3(ntiles), dim3(kWave), 0, s, a);
-    else hipLaunchKernelGGL((stage1v_kernel<T, N, false>), dim3(ntiles), dim3(kWave), 0, s, a);
-  }
+  if (a.bg_u) stage_bg<T, N, true>(nv, un, a, ntiles, s);
+  else stage_bg<T, N, false>(nv, un, a, ntiles, s);
   return hipGetLastError();
 }
 

@@ -273,6 +273,7 @@ const char* coarse_mismatch(const dg_ctx* c, const dg_nn* nn, bool* fluct = null
   if (c->cfg.storage != DG_F32) return "the learned correction needs FP32 storage";
   if (c->cfg.vbc != DG_VBC_PERIODIC) return "the learned correction assumes periodic velocity boundaries";
   if (c->cfg.layout != DG_LAYOUT_DENSE) return "the learned correction needs DG_LAYOUT_DENSE states";
+  if (c->bg) return "the learned correction needs whole-f states (no background set)";
   if (!nn) return nullptr;
   const int n = c->L.n, nb = n * n * n;
   if (nn->N.sizes[0] != 7 * nb + n && nn->N.sizes[0] != 8 * nb + n) return "network input width must be 7 n^3 + n or 8 n^3 + n";
@@ -519,6 +520,7 @@ dg_status dg_project(dg_ctx* fine, dg_ctx* coarse, const void* f_fine, void* f_c
   if (F.nv != C.nv) return dgi::fail(coarse, DG_ERR_INVALID, "dg_project: grids differ in dimension");
   if (F.layout != DG_LAYOUT_DENSE || C.layout != DG_LAYOUT_DENSE)
     return dgi::fail(coarse, DG_ERR_INVALID, "dg_project: states must use DG_LAYOUT_DENSE");
+  if (fine->bg || coarse->bg) return dgi::fail(coarse, DG_ERR_INVALID, "dg_project: states must be whole f (no background)");
   const int naxes = 1 + F.nv;
   int r[3] = {1, 1, 1};
   for (int a = 0; a < naxes; ++a) {
@@ -639,6 +641,7 @@ dg_status dg_nn_to_elements(dg_ctx* coarse, const void* x, const void* sub, floa
   if (coarse->cfg.nv != 2) return dgi::fail(coarse, DG_ERR_INVALID, "the learned correction needs a 1D2V grid");
   if (coarse->cfg.layout != DG_LAYOUT_DENSE)
     return dgi::fail(coarse, DG_ERR_INVALID, "the learned correction needs DG_LAYOUT_DENSE states");
+  if (coarse->bg) return dgi::fail(coarse, DG_ERR_INVALID, "the learned correction needs whole-f states (no background set)");
   const bool f64 = coarse->cfg.storage == DG_F64;
   if (!std::isfinite(scale)) return dgi::fail(coarse, DG_ERR_INVALID, "dg_nn_to_elements: scale must be finite");
   NN_TRY(dgi::enter(coarse));

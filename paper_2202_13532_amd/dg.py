@@ -27,7 +27,7 @@ EXPORTED = ["dg_workspace_bytes", "dg_init", "dg_destroy", "dg_rhs", "dg_poisson
             "dg_nn_set_params", "dg_nn_get_params", "dg_nn_forward", "dg_nn_loss_grad", "dg_nn_adamw",
             "dg_projection_matrix", "dg_project", "dg_nn_features", "dg_nn_features_raw", "dg_nn_to_elements",
             "dg_nn_column_stats", "dg_nn_rk_step", "dg_nn_last_error", "dg_state_elems", "dg_state_pack",
-            "dg_state_unpack", "dg_rhs_static"]
+            "dg_state_unpack", "dg_rhs_static", "dg_set_background"]
 
 
 class dg_config(ctypes.Structure):
@@ -113,6 +113,7 @@ def lib():
         "dg_state_pack": (I, [P, P, P]),
         "dg_state_unpack": (I, [P, P, P]),
         "dg_rhs_static": (I, [cfgp, P, P, P, P]),
+        "dg_set_background": (I, [P, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -185,6 +186,14 @@ def dg_rhs(ctx, f, E, rhs):
 
 def dg_rhs_static(cfg, f, E, rhs, stream=None):
     _check(lib().dg_rhs_static(ctypes.byref(cfg), _ptr(f), _ptr(E), _ptr(rhs), ctypes.c_void_p(stream)), None)
+
+
+def dg_set_background(ctx, f0=None):
+    if f0 is None:
+        _check(lib().dg_set_background(ctx, None), ctx)
+        return
+    a = np.ascontiguousarray(f0, dtype=np.float64)
+    _check(lib().dg_set_background(ctx, _dptr(a)), ctx)
 
 
 def dg_poisson(ctx, f, E, coeffs=None):
@@ -357,6 +366,15 @@ class Solver:
 
     def dt_max(self, max_abs_E=0.0):
         return dg_dt_max(self.ctx, max_abs_E)
+
+    def set_background(self, f0=None):
+        """x-uniform background f0 (host, [Nu*n, Nv*n] or [Nv*n]); states then hold f - f0."""
+        if f0 is not None:
+            nvn = self.nelem[-1] * self.n
+            nu = self.nelem[1] * self.n if self.nv == 2 else 1
+            f0 = np.asarray(f0, dtype=np.float64).reshape(nu, nvn) if self.nv == 2 else \
+                np.asarray(f0, dtype=np.float64).reshape(nvn)
+        dg_set_background(self.ctx, f0)
 
 
 # ---------------- batches ----------------

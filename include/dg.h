@@ -166,6 +166,28 @@ dg_status dg_rk_step(dg_ctx* ctx, void* f, double dt, int32_t nsteps, dg_diag* h
  * kernels that follow it.  Same CFL and finiteness checks as dg_rk_step.   */
 dg_status dg_profile_step(dg_ctx* ctx, void* f, double dt, int32_t nsteps, double* host_ms);
 
+/* ---------- spectral tools on the x grid (Sec. 5.3) ---------------------- */
+
+/* Fourier coefficients of arbitrary nodal data on the x grid through the
+ * connection tensor (eq. spectral_transform): coeffs (device, 2*pmax
+ * doubles, re/im) <- c_p = sum_mj T_p^{mj} g_mj for p = 1..pmax, g (device,
+ * Nx*n doubles).  pmax is the context's (dg_config.pmax), which may exceed
+ * Nx: the paper finds the transform accurate past the DFT Nyquist limit
+ * (Sec. 5.3.1, errors figure).                                              */
+dg_status dg_fourier(dg_ctx* ctx, const double* g, double* coeffs);
+
+/* Global spectral filter along x (Sec. 5.3: a global filter for
+ * anti-aliasing): every (u, v) node's x profile of f_in is replaced by its
+ * truncated Fourier series c_0 + sum_{p=1..pmax} 2 Re(sigma_p c_p e^{i k_p x})
+ * evaluated at the x nodes, c_p from the connection tensor; sigma (host,
+ * pmax doubles) weights the modes (all ones: the projection onto the first
+ * pmax modes; e.g. exp(-a (p / pmax)^s): an exponential filter).  f_in and
+ * f_out are states of the context's layout and dtype, not overlapping.
+ * The (Nx n) x (Nx n) filter matrix is built on the host in FP64 and applied
+ * on the device in the storage precision; Nx n <= 4096 (DG_ERR_UNSUPPORTED
+ * beyond).  Waits.                                                          */
+dg_status dg_filter_x(dg_ctx* ctx, const double* sigma, const void* f_in, void* f_out);
+
 /* delta-f storage (Sec. 2: the weak form is linear in f for a given field, so
  * L(f0 + g) = L(f0) + L(g)).  f0_host: an x-uniform background f0(u, v) as
  * host FP64 nodal values, dense [Nu*n][Nv*n] (1D2V) or [Nv*n] (1D1V), which

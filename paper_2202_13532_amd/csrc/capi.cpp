@@ -28,6 +28,8 @@ constexpr size_t kAlign = 256;
 // stores when a run's three state buffers do not fit in it.
 constexpr size_t kLastLevelCache = size_t(256) << 20;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+// dg_filter_x keeps a dense (Nx n) x (Nx n) matrix in the workspace
+constexpr size_t kMaxFilterNodes = 4096;
 
 std::mutex g_err_mu;
 std::string g_init_error = "no error";
@@ -100,6 +102,8 @@ Layout make_layout(const dg_config* c, bool stage_buffers = true) {
   L.off_bgu = take(stage_buffers ? vrows * L.lpitch * L.esize : 0);
   L.off_bgb = take(stage_buffers && c->nv == 2 ? vrows * L.lpitch * L.esize : 0);
   L.off_bg64 = take(stage_buffers ? vrows * L.Nv * L.n * 8 : 0);
+  // x-filter matrix (dg_filter_x), for up to kMaxFilterNodes x nodes
+  L.off_M = take(stage_buffers && nx <= kMaxFilterNodes ? nx * nx * L.esize : 0);
   L.total = o;
   return L;
 }
@@ -721,6 +725,56 @@ dg_status dg_diagnostics(dg_ctx* ctx, const void* f, dg_diag* host_out) {
   host_out->step = 0;
   DG_TRY(leave(ctx));
   return host_out->finite ? DG_OK : fail(ctx, DG_ERR_NONFINITE, "dg_diagnostics: non-finite moments");
+}
+
+dg_status dg_fourier(dg_ctx* ctx, const double* g, double* coeffs) {
+  if (!ctx) return DG_ERR_INVALID;
+  if (!g || !coeffs) return fail(ctx, DG_ERR_INVALID, "dg_fourier: NULL argument");
+  const Layout& L = ctx->L;
+  DG_TRY(enter(ctx));
+  hipError_t e = dgk::launch_fourier(ctx->at<double>(L.off_T), g, L.Nx * L.n, L.pmax, coeffs, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "fourier kernel launch");
+  return leave(ctx);
+}
+
+dg_status dg_filter_x(dg_ctx* ctx, const double* sigma, const void* f_in, void* f_out) {
+  if (!ctx) return DG_ERR_INVALID;
+  if (!sigma || !f_in || !f_out) return fail(ctx, DG_ERR_INVALID, "dg_filter_x: NULL argument");
+  if (f_in == f_out) return fail(ctx, DG_ERR_INVALID, "dg_filter_x: f_in and f_out must not overlap");
+  const Layout& L = ctx->L;
+  const dg_config& C = ctx->cfg;
+  const int R = L.Nx * L.n, n = L.n;
+  if (static_cast<size_t>(R) > kMaxFilterNodes)
+    return fail(ctx, DG_ERR_UNSUPPORTED, "dg_filter_x: more than 4096 x nodes");
+  for (int p = 0; p < L.pmax; ++p)
+    if (!std::isfinite(sigma[p])) return fail(ctx, DG_ERR_INVALID, "dg_filter_x: sigma is not finite");
+  // M[r][q] = T_0^q + sum_{p=1..pmax} 2 Re(sigma_p T_p^q e^{i k_p x_r}) (eq. spectral_transform,
+  // then eq. fourier_series truncated at pmax with the weights sigma), T_0^{mj} = (dx/L) w_j / 2
+  const auto T = dgh::connection_tensor(ctx->basis, L.Nx, C.lo[0], C.hi[0], L.pmax);
+  const std::vector<double> xn = axis_nodes(ctx->basis, L.Nx, C.lo[0], C.hi[0]);
+  const double Lx = C.hi[0] - C.lo[0], dx = Lx / L.Nx;
+  std::vector<double> M(static_cast<size_t>(R) * R);
+  for (int r = 0; r < R; ++r) {
+    std::vector<std::complex<double>> z(L.pmax);
+    for (int p = 1; p <= L.pmax; ++p) z[p - 1] = sigma[p - 1] * std::polar(1.0, 2.0 * M_PI * p / Lx * xn[r]);
+    for (int q = 0; q < R; ++q) {
+      double v = dx / Lx * ctx->basis.w[q % n] * 0.5;
+      for (int p = 1; p <= L.pmax; ++p) v += 2.0 * (z[p - 1] * T[static_cast<size_t>(p - 1) * R + q]).real();
+      M[static_cast<size_t>(r) * R + q] = v;
+    }
+  }
+  DG_TRY(enter(ctx));
+  if (ctx->f64()) {
+    DG_HIP(ctx, hipMemcpyAsync(ctx->ws + L.off_M, M.data(), M.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  } else {
+    std::vector<float> Mf(M.begin(), M.end());
+    DG_HIP(ctx, hipMemcpyAsync(ctx->ws + L.off_M, Mf.data(), Mf.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    DG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  hipError_t e = dgk::launch_xfilter(ctx->f64(), f_in, f_out, ctx->ws + L.off_M, R, L.selems / R, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "x-filter kernel launch");
+  DG_HIP(ctx, hipStreamSynchronize(ctx->stream));   // M is host memory of this call
+  return leave(ctx);
 }
 
 dg_status dg_set_background(dg_ctx* ctx, const double* f0) {

@@ -21,7 +21,7 @@ struct Layout {
   size_t selems = 0;            // values in a state array
   size_t off_B, off_C, off_part, off_mom, off_dens, off_E, off_cpart, off_mpart, off_coef, off_ring,
       off_last, off_ctr, off_T, off_z1, off_wx, off_wu, off_wv, off_uc, off_vc, off_uc64, off_vc64,
-      off_bgu, off_bgb, off_bg64, total;
+      off_bgu, off_bgb, off_bg64, off_M, total;
 };
 
 }  // namespace dgi

@@ -69,6 +69,10 @@ hipError_t launch_moments(int nv, int n, bool f64, const void* args, double* mom
 hipError_t launch_field(const FieldArgs& a, hipStream_t s);
 hipError_t launch_moments_reduce(const double* mom, int ntiles, double* ring, const int* counter, hipStream_t s);
 hipError_t launch_reset_counter(int* counter, hipStream_t s);
+// c_p (2*pmax doubles) = T (node-major [nodes][pmax] complex) applied to g (nodes)
+hipError_t launch_fourier(const double* T, const double* g, int nodes, int pmax, double* out, hipStream_t s);
+// out = M in along the x rows: M R x R, states R x C, storage precision
+hipError_t launch_xfilter(bool f64, const void* in, void* out, const void* M, int R, size_t C, hipStream_t s);
 // dense rows of nvn values <-> rows of lp values in chunks of cp (tvn used);
 // pack writes rows*lp values (zeros in unused slots), unpack rows*nvn
 hipError_t launch_repack(bool pack, bool f64, const void* in, void* out, size_t rows, unsigned lp, unsigned cp,

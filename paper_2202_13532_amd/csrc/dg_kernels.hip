@@ -1004,6 +1004,76 @@ __global__ void moments_reduce_kernel(const double* mom, int ntiles, double* rin
 __global__ void reset_counter_kernel(int* c) { *c = 0; }
 
 // -------------------------------------------------------------------------
+// Spectral tools on the x grid (Sec. 5.3).
+//   fourier_kernel: c_p = sum_q T_p^q g_q for p = 1..pmax (eq. spectral_transform)
+//     on arbitrary nodal values g; block b serves modes 64b..64b+63, four
+//     groups of 64 threads each add a contiguous quarter of the nodes, the
+//     quarters are then added in order.
+//   xfilter_kernel: out[r, c] = sum_q M[r, q] in[q, c] for a state seen as an
+//     (Nx n) x C matrix (x outermost); block (bx, by) computes a 64-column x
+//     64-row tile through 16-deep LDS slabs of M and of the state.
+// -------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) fourier_kernel(const double* __restrict__ T, const double* __restrict__ g,
+                                                      int nodes, int pmax, double* __restrict__ out) {
+  __shared__ double red[2][256];
+  const int tid = threadIdx.x, p = blockIdx.x * 64 + tid % 64, grp = tid / 64;
+  double cr = 0.0, ci = 0.0;
+  if (p < pmax) {
+    const int q0 = grp * nodes / 4, q1 = (grp + 1) * nodes / 4;
+    for (int q = q0; q < q1; ++q) {
+      const double v = g[q];
+      const double* t = T + 2 * (static_cast<size_t>(q) * pmax + p);
+      cr = __builtin_fma(t[0], v, cr);
+      ci = __builtin_fma(t[1], v, ci);
+    }
+  }
+  red[0][tid] = cr;
+  red[1][tid] = ci;
+  __syncthreads();
+  if (tid < 64 && p < pmax) {
+    out[2 * p] = (red[0][tid] + red[0][64 + tid]) + (red[0][128 + tid] + red[0][192 + tid]);
+    out[2 * p + 1] = (red[1][tid] + red[1][64 + tid]) + (red[1][128 + tid] + red[1][192 + tid]);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) xfilter_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                      const T* __restrict__ M, int R, size_t C) {
+  __shared__ T Ms[64][17];
+  __shared__ T Fs[16][64];
+  const int tid = threadIdx.x, lane = tid % 64, grp = tid / 64;
+  const size_t col = static_cast<size_t>(blockIdx.x) * 64 + lane;
+  const int r0 = blockIdx.y * 64;
+  T acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = T(0);
+  for (int k0 = 0; k0 < R; k0 += 16) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int kk = grp * 4 + i, q = k0 + kk;
+      Fs[kk][lane] = (q < R && col < C) ? in[static_cast<size_t>(q) * C + col] : T(0);
+      const int e = tid + 256 * i, mr = e / 16, mk = e % 16;   // 64 x 16 slab of M
+      Ms[mr][mk] = (r0 + mr < R && k0 + mk < R) ? M[static_cast<size_t>(r0 + mr) * R + k0 + mk] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const T fv = Fs[kk][lane];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = fmadd(Ms[grp * 16 + r][kk], fv, acc[r]);
+    }
+    __syncthreads();
+  }
+  if (col < C) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = r0 + grp * 16 + r;
+      if (row < R) out[static_cast<size_t>(row) * C + col] = acc[r];
+    }
+  }
+}
+
+// -------------------------------------------------------------------------
 // Batched persistent stage kernels: many independent runs (1D1V and 1D2V, n
 // in 2..12, FP32 storage).  Runs are grouped by kind (n, velocity dimension);
 // each kind gets one persistent launch per RK stage, specialised like the
@@ -1182,6 +1252,22 @@ hipError_t launch_field_batched(const FieldArgs* fa, const int2* xitems, int nxi
   return hipGetLastError();
 }
 
+
+hipError_t launch_fourier(const double* T, const double* g, int nodes, int pmax, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(fourier_kernel, dim3((pmax + 63) / 64), dim3(256), 0, s, T, g, nodes, pmax, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_xfilter(bool f64, const void* in, void* out, const void* M, int R, size_t C, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>((C + 63) / 64), static_cast<unsigned>((R + 63) / 64));
+  if (f64)
+    hipLaunchKernelGGL(xfilter_kernel<double>, grid, dim3(256), 0, s, static_cast<const double*>(in),
+                       static_cast<double*>(out), static_cast<const double*>(M), R, C);
+  else
+    hipLaunchKernelGGL(xfilter_kernel<float>, grid, dim3(256), 0, s, static_cast<const float*>(in),
+                       static_cast<float*>(out), static_cast<const float*>(M), R, C);
+  return hipGetLastError();
+}
 
 hipError_t launch_reset_counter(int* counter, hipStream_t s) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);

@@ -27,7 +27,7 @@ EXPORTED = ["dg_workspace_bytes", "dg_init", "dg_destroy", "dg_rhs", "dg_poisson
             "dg_nn_set_params", "dg_nn_get_params", "dg_nn_forward", "dg_nn_loss_grad", "dg_nn_adamw",
             "dg_projection_matrix", "dg_project", "dg_nn_features", "dg_nn_features_raw", "dg_nn_to_elements",
             "dg_nn_column_stats", "dg_nn_rk_step", "dg_nn_last_error", "dg_state_elems", "dg_state_pack",
-            "dg_state_unpack", "dg_rhs_static", "dg_set_background"]
+            "dg_state_unpack", "dg_rhs_static", "dg_set_background", "dg_fourier", "dg_filter_x"]
 
 
 class dg_config(ctypes.Structure):
@@ -114,6 +114,8 @@ def lib():
         "dg_state_unpack": (I, [P, P, P]),
         "dg_rhs_static": (I, [cfgp, P, P, P, P]),
         "dg_set_background": (I, [P, dp]),
+        "dg_fourier": (I, [P, P, P]),
+        "dg_filter_x": (I, [P, dp, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -186,6 +188,15 @@ def dg_rhs(ctx, f, E, rhs):
 
 def dg_rhs_static(cfg, f, E, rhs, stream=None):
     _check(lib().dg_rhs_static(ctypes.byref(cfg), _ptr(f), _ptr(E), _ptr(rhs), ctypes.c_void_p(stream)), None)
+
+
+def dg_fourier(ctx, g, coeffs):
+    _check(lib().dg_fourier(ctx, _ptr(g), _ptr(coeffs)), ctx)
+
+
+def dg_filter_x(ctx, sigma, f_in, f_out):
+    sg = np.ascontiguousarray(sigma, dtype=np.float64)
+    _check(lib().dg_filter_x(ctx, _dptr(sg), _ptr(f_in), _ptr(f_out)), ctx)
 
 
 def dg_set_background(ctx, f0=None):
@@ -366,6 +377,28 @@ class Solver:
 
     def dt_max(self, max_abs_E=0.0):
         return dg_dt_max(self.ctx, max_abs_E)
+
+    def fourier(self, g):
+        """c_p, p = 1..pmax (complex numpy array), of nodal values g (device float64, Nx*n) on the x grid."""
+        t = self.torch
+        if (not isinstance(g, t.Tensor) or g.device.type != "cuda" or g.dtype != t.float64
+                or not g.is_contiguous() or g.numel() != self.nelem[0] * self.n):
+            raise DGError(DG_ERR_INVALID, "g must be a contiguous float64 device tensor of Nx*n values")
+        c = t.empty(2 * self.pmax, dtype=t.float64, device=self.device)
+        dg_fourier(self.ctx, g, c)
+        h = c.cpu().numpy().reshape(-1, 2)
+        return h[:, 0] + 1j * h[:, 1]
+
+    def filter_x(self, f, sigma, out=None):
+        """Global x filter of a state: modes p = 1..pmax weighted by sigma (host array of pmax)."""
+        self._check_state(f)
+        sigma = np.asarray(sigma, dtype=np.float64).reshape(-1)
+        if sigma.size != self.pmax:
+            raise DGError(DG_ERR_INVALID, "sigma needs pmax = %d weights" % self.pmax)
+        out = self.empty_state() if out is None else out
+        self._check_state(out)
+        dg_filter_x(self.ctx, sigma, f, out)
+        return out
 
     def set_background(self, f0=None):
         """x-uniform background f0 (host, [Nu*n, Nv*n] or [Nv*n]); states then hold f - f0."""

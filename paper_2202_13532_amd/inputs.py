@@ -123,3 +123,12 @@ def broadcast_coords(axes_nodes, xp=np):
         shp[2 * a], shp[2 * a + 1] = nodes.shape[0], nodes.shape[1]
         out.append(nodes.reshape(shp))
     return out
+
+
+def elliptic_cosine(x, sqrt_m):
+    """cn(4 K x | m) (period 1 in x, K the quarter period), the test function
+    of the paper's aliasing study (Sec. 5.3.1, errors figure)."""
+    from scipy import special
+    m = sqrt_m * sqrt_m
+    K = special.ellipk(m)
+    return special.ellipj(4.0 * K * np.asarray(x, dtype=np.float64), m)[1]

@@ -67,6 +67,44 @@ def make_state(torch, solver, wl):
     return solver.pack(f.to(solver.dtype).contiguous())   # into the solver's state layout
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_config_timings():
+    """The oracle's one RHS and one full SSP-RK3 step (Poisson at every stage)
+    on the 1D1V Landau workload (8192 DOF, FP64) and the 1D2V ring workload
+    (16.8 M DOF), timed once each."""
+    import numpy as np
+    from oracle import grid, lgl, rhs, rk
+    from paper_2202_13532_amd import workloads as W
+    out = []
+    for wl in (W.landau_1d1v_n4(), W.ring_1d2v_n8()):
+        g = grid.PhaseGrid(wl.nv, wl.n, wl.nelem, wl.lo, wl.hi, wl.omega_c)
+        f = np.broadcast_to(np.asarray(W.initial_state(wl, [ax.nodes for ax in g.axes], np), dtype=np.float64),
+                            g.shape).copy()
+        ops = lgl.operators(wl.n)
+        E = np.zeros((wl.nelem[0], wl.n))
+        t0 = time.perf_counter()
+        rhs.rhs(g, ops, f, E)
+        t_rhs = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rk.ssprk3_step(g, ops, f, 1e-4)
+        t_step = time.perf_counter() - t0
+        dof = g.dof()
+        out.append({"workload": wl.name, "dof": int(dof), "rhs_s": t_rhs, "rk3_step_s": t_step,
+                    "dof_stage_updates_per_s_rk3": 3 * dof / t_step})
+        del f
+    return out
+
+
 def cpu_baseline(wl, budget_s=12.0):
     """FP64 oracle, one RK stage on x elements [0, Nx/8) plus a 1-element halo."""
     import numpy as np
@@ -98,9 +136,10 @@ def cpu_baseline(wl, budget_s=12.0):
     el = time.perf_counter() - t0
     dof_inner = g.dof() * nx_sub // (nx_sub + 2)
     return {"value": dof_inner * reps / el, "unit": "DOF-updates/s per RK stage", "cores": int(cores),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": "%d RK stage(s) of the FP64 NumPy oracle on x elements [0,%d) of %d (+1-element halo), %d DOF each, %.1f s"
-                      % (reps, nx_sub, wl.nelem[0], dof_inner, el)}
+                      % (reps, nx_sub, wl.nelem[0], dof_inner, el),
+            "oracle_configs": oracle_config_timings()}
 
 
 def bench_sweep(args):
@@ -177,6 +216,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run two plain device copies of one state buffer (reference for HBM byte counters)")
+    ap.add_argument("--pattern-copy", action="store_true",
+                    help="print the bandwidth of a streaming copy and of a copy with the stage kernel's tile "
+                         "access pattern (no halos, no arithmetic) next to the stage kernels'")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -234,6 +276,20 @@ def main():
             buf.copy_(f)
         torch.cuda.synchronize()
         del buf
+    if args.pattern_copy:
+        state_bytes = f.numel() * f.element_size()
+        ms_lin = s.profile_copy(f, 0, 20)
+        ms_pat = s.profile_copy(f, 1, 20)
+        rec = {"metric": "copy references (GB/s, read + write)", "workload": wl.name, "storage": wl.storage,
+               "layout": layout, "state_bytes": state_bytes,
+               "linear_copy": {"ms": ms_lin, "GBs": 2 * state_bytes / (ms_lin / 1e3) / 1e9},
+               "tile_pattern_copy": {"ms": ms_pat, "GBs": 2 * state_bytes / (ms_pat / 1e3) / 1e9},
+               "stage_kernels_GBs_algorithmic": [b / (t / 1e3) / 1e9 for b, t in
+                                                 zip(bytes_per_launch, st_ms.mean(axis=0))],
+               "peak_GBs": HBM_PEAK_GBS}
+        print(json.dumps(rec), flush=True)
+        s.close()
+        return
     diag = s.diagnostics(f)
     line = {
         "metric": "phase-space DOF-updates/sec per RK stage (FP32) + % peak HBM BW",

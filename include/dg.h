@@ -205,6 +205,16 @@ dg_status dg_filter_x(dg_ctx* ctx, const double* sigma, const void* f_in, void* 
  * background.                                                               */
 dg_status dg_set_background(dg_ctx* ctx, const double* f0_host);
 
+/* Bandwidth references for the stage kernel (measurement only): `reps`
+ * launches of a copy of state `in` into state `out` (context layout and
+ * dtype, not overlapping) timed with HIP events on the context stream after
+ * one warm-up launch; *host_ms receives the mean per launch; waits.
+ * pattern 0: a plain streaming copy (16-byte accesses; the state's size
+ * rounded down to 16 bytes); pattern 1 (1D2V): the stage kernel's own access
+ * pattern -- its tiles, their order and store policy -- with no halos and no
+ * arithmetic.  Each moves 2 * dg_state_elems() * sizeof(storage) bytes.    */
+dg_status dg_profile_copy(dg_ctx* ctx, const void* in, void* out, int32_t pattern, int32_t reps, double* host_ms);
+
 /* Full diagnostics of state f (its own Poisson solve) into *host_out; waits.
  * The quantities are those the paper tracks over its runs (Sec. 6, energy
  * figure): mass, the domain-integrated field energy (the paper leaves its

@@ -727,6 +727,42 @@ dg_status dg_diagnostics(dg_ctx* ctx, const void* f, dg_diag* host_out) {
   return host_out->finite ? DG_OK : fail(ctx, DG_ERR_NONFINITE, "dg_diagnostics: non-finite moments");
 }
 
+dg_status dg_profile_copy(dg_ctx* ctx, const void* in, void* out, int32_t pattern, int32_t reps, double* host_ms) {
+  if (!ctx) return DG_ERR_INVALID;
+  if (!in || !out || !host_ms || reps < 1) return fail(ctx, DG_ERR_INVALID, "dg_profile_copy: bad argument");
+  if (in == out) return fail(ctx, DG_ERR_INVALID, "dg_profile_copy: in and out must not overlap");
+  if (pattern == 1 && ctx->cfg.nv != 2) return fail(ctx, DG_ERR_UNSUPPORTED, "dg_profile_copy: the tile pattern is 1D2V");
+  if (pattern != 0 && pattern != 1) return fail(ctx, DG_ERR_INVALID, "dg_profile_copy: pattern must be 0 or 1");
+  const Layout& L = ctx->L;
+  auto launch = [&]() -> hipError_t {
+    if (pattern == 0) return dgk::launch_linear_copy(in, out, L.selems * L.esize / 16 * 16, ctx->stream);
+    if (ctx->f64()) {
+      dgk::StageArgs<double> p;
+      fill_pack(ctx, &p, in, in, out, nullptr, nullptr, 0, 0, 0);
+      return dgk::launch_pattern_copy(2, L.n, true, &p, L.ntiles, ctx->stream);
+    }
+    dgk::StageArgs<float> p;
+    fill_pack(ctx, &p, in, in, out, nullptr, nullptr, 0, 0, 0);
+    return dgk::launch_pattern_copy(2, L.n, false, &p, L.ntiles, ctx->stream);
+  };
+  DG_TRY(enter(ctx));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  DG_HIP(ctx, hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = launch();   // warm-up launch
+  if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(ctx, e, "dg_profile_copy");
+  *host_ms = ms / reps;
+  return leave(ctx);
+}
+
 dg_status dg_fourier(dg_ctx* ctx, const double* g, double* coeffs) {
   if (!ctx) return DG_ERR_INVALID;
   if (!g || !coeffs) return fail(ctx, DG_ERR_INVALID, "dg_fourier: NULL argument");

@@ -1004,6 +1004,52 @@ __global__ void moments_reduce_kernel(const double* mom, int ntiles, double* rin
 __global__ void reset_counter_kernel(int* c) { *c = 0; }
 
 // -------------------------------------------------------------------------
+// Copy references for the bandwidth measurements (bench.py --pattern-copy):
+//   linear_copy_kernel: 16-byte loads and stores, grid-stride;
+//   pattern_copy_kernel: the 1D2V stage kernel's access pattern without its
+//     halos or arithmetic: one wave per tile (same tiles, XCD remap and
+//     buffer resources), the tile's n x n rows of one v chunk loaded, then
+//     stored (unused slots of padded rows written as zeros).
+// -------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) linear_copy_kernel(const float4* __restrict__ in, float4* __restrict__ out,
+                                                          size_t n16) {
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n16;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    out[i] = in[i];
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(kWave) pattern_copy_kernel(StageArgs<T> a) {
+  using B = Buf<T>;
+  constexpr unsigned S = sizeof(T);
+  constexpr int TV = kWave / N;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const unsigned lane = threadIdx.x;
+  const int vc = bid % a.nvchunks, t1 = bid / a.nvchunks, iu = t1 % a.Nu, ix = t1 / a.Nu;
+  const int tva = min(TV, a.Nv - vc * TV);
+  const unsigned NUn = static_cast<unsigned>(a.Nu) * N, LP = a.lpitch, CP = a.cpitch, m0 = vc * CP;
+  const size_t xstride = static_cast<size_t>(N) * NUn * LP;
+  const unsigned xbytes = static_cast<unsigned>(xstride * S), rowb = LP * S;
+  const unsigned vo = lane < static_cast<unsigned>(tva * N) ? lane * S : kOffOOB;
+  const unsigned vs = (lane < CP && m0 + lane < LP) ? lane * S : kOffOOB;
+  const auto rf = xelem_rsrc(a.fin, xstride, ix, xbytes);
+  const auto ro = xelem_rsrc(a.out, xstride, ix, xbytes);
+  T f[N][N];
+#pragma unroll
+  for (int jx = 0; jx < N; ++jx)
+#pragma unroll
+    for (int ju = 0; ju < N; ++ju) f[jx][ju] = B::ld(rf, vo + ((jx * NUn + iu * N) * LP + m0) * S, ju * rowb);
+#pragma unroll
+  for (int jx = 0; jx < N; ++jx)
+#pragma unroll
+    for (int ju = 0; ju < N; ++ju) {
+      const unsigned o = vs + ((jx * NUn + iu * N) * LP + m0) * S;
+      if (a.nt_store) B::st_nt(f[jx][ju], ro, o, ju * rowb);
+      else B::st(f[jx][ju], ro, o, ju * rowb);
+    }
+}
+
+// -------------------------------------------------------------------------
 // Spectral tools on the x grid (Sec. 5.3).
 //   fourier_kernel: c_p = sum_q T_p^q g_q for p = 1..pmax (eq. spectral_transform)
 //     on arbitrary nodal values g; block b serves modes 64b..64b+63, four
@@ -1252,6 +1298,25 @@ hipError_t launch_field_batched(const FieldArgs* fa, const int2* xitems, int nxi
   return hipGetLastError();
 }
 
+
+hipError_t launch_linear_copy(const void* in, void* out, size_t bytes, hipStream_t s) {
+  const size_t n16 = bytes / 16;
+  hipLaunchKernelGGL(linear_copy_kernel, dim3(8192), dim3(256), 0, s, static_cast<const float4*>(in),
+                     static_cast<float4*>(out), n16);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t pattern_copy_t(int nv, const void* args, int ntiles, hipStream_t s) {
+  if (nv != 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((pattern_copy_kernel<T, N>), dim3(ntiles), dim3(kWave), 0, s, *static_cast<const StageArgs<T>*>(args));
+  return hipGetLastError();
+}
+
+hipError_t launch_pattern_copy(int nv, int n, bool f64, const void* args, int ntiles, hipStream_t s) {
+  if (f64) { DG_DISPATCH_N(pattern_copy_t, double, nv, args, ntiles, s) }
+  DG_DISPATCH_N(pattern_copy_t, float, nv, args, ntiles, s)
+}
 
 hipError_t launch_fourier(const double* T, const double* g, int nodes, int pmax, double* out, hipStream_t s) {
   hipLaunchKernelGGL(fourier_kernel, dim3((pmax + 63) / 64), dim3(256), 0, s, T, g, nodes, pmax, out);

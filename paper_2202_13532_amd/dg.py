@@ -27,7 +27,8 @@ EXPORTED = ["dg_workspace_bytes", "dg_init", "dg_destroy", "dg_rhs", "dg_poisson
             "dg_nn_set_params", "dg_nn_get_params", "dg_nn_forward", "dg_nn_loss_grad", "dg_nn_adamw",
             "dg_projection_matrix", "dg_project", "dg_nn_features", "dg_nn_features_raw", "dg_nn_to_elements",
             "dg_nn_column_stats", "dg_nn_rk_step", "dg_nn_last_error", "dg_state_elems", "dg_state_pack",
-            "dg_state_unpack", "dg_rhs_static", "dg_set_background", "dg_fourier", "dg_filter_x"]
+            "dg_state_unpack", "dg_rhs_static", "dg_set_background", "dg_fourier", "dg_filter_x",
+            "dg_profile_copy"]
 
 
 class dg_config(ctypes.Structure):
@@ -116,6 +117,7 @@ def lib():
         "dg_set_background": (I, [P, dp]),
         "dg_fourier": (I, [P, P, P]),
         "dg_filter_x": (I, [P, dp, P, P]),
+        "dg_profile_copy": (I, [P, P, P, I, I, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -188,6 +190,12 @@ def dg_rhs(ctx, f, E, rhs):
 
 def dg_rhs_static(cfg, f, E, rhs, stream=None):
     _check(lib().dg_rhs_static(ctypes.byref(cfg), _ptr(f), _ptr(E), _ptr(rhs), ctypes.c_void_p(stream)), None)
+
+
+def dg_profile_copy(ctx, f_in, f_out, pattern, reps):
+    ms = np.zeros(1)
+    _check(lib().dg_profile_copy(ctx, _ptr(f_in), _ptr(f_out), int(pattern), int(reps), _dptr(ms)), ctx)
+    return float(ms[0])
 
 
 def dg_fourier(ctx, g, coeffs):
@@ -366,6 +374,12 @@ class Solver:
     def step(self, f, dt, nsteps=1, diag=False):
         self._check_state(f)
         return dg_rk_step(self.ctx, f, dt, nsteps, diag)
+
+    def profile_copy(self, f, pattern, reps=20):
+        """Mean ms of a copy of state f: pattern 0 streaming, 1 the stage kernel's tile pattern."""
+        self._check_state(f)
+        out = self.empty_state()
+        return dg_profile_copy(self.ctx, f, out, pattern, reps)
 
     def profile_step(self, f, dt, nsteps=1):
         self._check_state(f)

@@ -1,16 +1,20 @@
 """Learned coarse-grid correction end to end, judged by fine-grid runs.
 
-Small version of the training pipeline (4 fine runs, 16 snapshots each, 8
-epochs) on the real grids (fine 32^3 x n=8, coarse 16^3 x n=4).  Checked:
-* training reduces the closure error on the training set below 0.4, and on
-  a held-out run the relative error ||T - NN(X)|| / ||T|| of the per-element
-  RHS correction is below 0.6 (the untrained, near-zero network scores 1.0;
-  this small training set reaches 0.40, the full one 0.13);
-* corrected coarse runs stay finite and conserve mass (the correction is
-  mass-neutral per element);
-* against the FP64 fine run, the corrected field-energy history stays within
-  2 % (relative L2) over 250 coarse steps (the bar of the learned-correction
-  workload), as does the plain coarse one.
+Workload (the pipeline's default): 1D2V, L = 4 pi, B = 0.05, ring/Maxwellian
+mixtures (ring fraction in [0, 0.3], v_t in [0.9, 1.1]) with a 0.4 density
+perturbation: strong nonlinear Landau damping whose velocity filamentation
+the coarse grid (16^3 elements, n = 4) cannot follow after the initial
+damping.  Small training set (8 fine runs x 32 snapshots, 10 epochs) on the
+real grids (fine 32^3 x n = 8, FP64); evaluation on three held-out seeds over
+2000 coarse steps (t = 18.6) against the FP64 fine run:
+* the whole field-energy history (relative L2, the bar of the workload):
+  corrected coarse within 2 % and closer to the fine run than plain coarse;
+* its second half, after the initial damping (the field energy has fallen
+  by two to three decades): plain coarse is off by several times the fine
+  values; the correction must remove at least 40 % of that error;
+* at least 10x fewer DOF-updates per simulated time unit than the fine grid;
+* the correction keeps mass (it is mass-neutral per element) and training
+  lowers the closure error.
 """
 import math
 
@@ -24,13 +28,14 @@ from paper_2202_13532_amd import learned  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 
-def test_learned_correction_trains_and_runs():
-    print("learned pipeline (small)", flush=True)
-    cfg = learned.Config(train_seeds=[0, 1, 2, 3], snapshots_per_run=16, snapshot_stride=110, epochs=8)
+def test_learned_correction_gains_over_plain_coarse():
+    print("learned pipeline (small training set)", flush=True)
+    cfg = learned.Config(train_seeds=list(range(8)), snapshots_per_run=32, snapshot_stride=440, epochs=10)
     lc = learned.LearnedCorrection(cfg)
     st, fl, tg = lc.generate(cfg.train_seeds)
     lc.fit_normalisation(st, fl, tg)
     X, T = lc.dataset(st, fl, tg)
+    del st, fl, tg
     lc.init_params()
     err0 = lc.relative_error(X, T)
     assert 0.9 < err0 < 1.1
@@ -38,26 +43,19 @@ def test_learned_correction_trains_and_runs():
     assert all(math.isfinite(l) for _, l in hist)
     err1 = lc.relative_error(X, T)
     print("training-set closure relative error", err0, "->", err1, flush=True)
-    assert err1 < 0.4
-    hs, hf, ht = lc.generate([1000], nsnap=6, stride=220)
-    Xh, Th = lc.dataset(hs, hf, ht)
-    err_h = lc.relative_error(Xh, Th)
-    print("held-out closure relative error", err_h, flush=True)
-    assert err_h < 0.6
-    # minibatches of whole snapshots (4 per AdamW step) train as well
-    lc4 = learned.LearnedCorrection(learned.Config(train_seeds=[0, 1, 2, 3], snapshots_per_run=16,
-                                                   snapshot_stride=110, epochs=24, snapshots_per_step=4, lr=2e-3))
-    lc4.mean, lc4.inv_std, lc4.target_scale = lc.mean, lc.inv_std, lc.target_scale
-    lc4.init_params()
-    lc4.train(X, T)
-    err4 = lc4.relative_error(X, T)
-    print("training-set closure relative error, 4 snapshots per step:", err4, flush=True)
-    assert err4 < 0.5
-    lc4.close()
-    ev = lc.evaluate(1000, 250, checkpoints=2)
-    fe = ev["field_energy_rel_l2"]
-    print("field energy rel L2", fe, "mass drift", ev["mass_drift"], flush=True)
-    assert fe["coarse_nn"] < 0.02 and fe["plain_coarse"] < 0.02
-    assert ev["mass_drift"]["coarse_nn"] < 1e-5
-    assert np.all(np.isfinite(ev["history"]["nn"]))
+    assert err1 < 0.6
+    for seed in (1000, 1001, 1002):
+        ev = lc.evaluate(seed, 2000, checkpoints=4)
+        fe, late = ev["field_energy_rel_l2"], ev["field_energy_rel_l2_late"]
+        dofr = ev["dof_updates_per_sim_time"]["fine"] / ev["dof_updates_per_sim_time"]["coarse"]
+        print("seed %d: whole history plain %.4f nn %.4f; after t = %.1f plain %.3f nn %.3f; DOF ratio %.0f"
+              % (seed, fe["plain_coarse"], fe["coarse_nn"], late["from_t"], late["plain_coarse"], late["coarse_nn"],
+                 dofr), flush=True)
+        assert fe["coarse_nn"] <= 0.02
+        assert fe["coarse_nn"] < fe["plain_coarse"]
+        assert late["plain_coarse"] > 1.0            # the coarse grid alone is far off after the transient
+        assert late["coarse_nn"] < 0.6 * late["plain_coarse"]
+        assert dofr >= 10.0
+        assert ev["mass_drift"]["coarse_nn"] < 1e-5
+        assert np.all(np.isfinite(ev["history"]["nn"]))
     lc.close()

@@ -142,15 +142,17 @@ def cpu_baseline(wl, budget_s=12.0):
             "oracle_configs": oracle_config_timings()}
 
 
-def bench_sweep(args):
-    """Uneven batch of 64 runs (32 x 1D1V, 32 x 1D2V, n 4..9): one persistent
-    stage launch per RK stage for all runs, against the same runs stepped one
-    after another with their own graphs."""
+def sweep_record(steps, warmup, layout=None, bw_single=None):
+    """Uneven batch of 64 runs (32 x 1D1V, 32 x 1D2V, n 4..9): persistent
+    stage launches (one per kind of run and RK stage) under the tuner's
+    choices, against the same runs stepped one after another with their own
+    graphs.  bw_single: algorithmic GB/s of the single-run stage kernels, to
+    express the sweep's step time against its algorithmic-byte time."""
     import torch
     from paper_2202_13532_amd import dg
     from paper_2202_13532_amd import workloads as W
     wls = W.uneven_sweep(64)
-    lay = [(args.layout or "vpad") if w.nv == 2 else "dense" for w in wls]   # padded v rows for 1D2V runs
+    lay = [(layout or "vpad") if w.nv == 2 else "dense" for w in wls]   # padded v rows for 1D2V runs
     cfgs = [dg.make_config(w.nv, w.n, w.nelem, w.lo, w.hi, w.omega_c, layout=l) for w, l in zip(wls, lay)]
     solos = [dg.Solver(w.nv, w.n, w.nelem, w.lo, w.hi, w.omega_c, layout=l) for w, l in zip(wls, lay)]
     states, dts = [], []
@@ -162,46 +164,58 @@ def bench_sweep(args):
     dof = sum(w.dof() for w in wls)
     print("[bench] sweep: %d runs, %d DOF" % (len(wls), dof), file=sys.stderr, flush=True)
     b = dg.Batch(cfgs)
+    t0 = time.perf_counter()
     tuned_ms = b.tune(states, dts, 3)
-    if args.warmup > 0:
-        b.step(states, dts, args.warmup)
+    t_tune = time.perf_counter() - t0
+    if warmup > 0:
+        b.step(states, dts, warmup)
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
-    b.step(states, dts, args.steps)
+    b.step(states, dts, steps)
     end.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
     # the same runs one after another (each with its own captured step graph)
     for so, f, dt in zip(solos, states, dts):
-        so.step(f, dt, max(1, args.warmup))
+        so.step(f, dt, max(1, min(warmup, 10)))
     torch.cuda.synchronize()
     start.record()
     for so, f, dt in zip(solos, states, dts):
-        so.step(f, dt, args.steps)
+        so.step(f, dt, steps)
     end.record()
     torch.cuda.synchronize()
     ms_solo = start.elapsed_time(end)
-    value = dof * 3 * args.steps / (ms / 1e3)
     alg_bytes = 32 * dof   # FP32: 8 + 12 + 12 bytes per DOF per step
-    line = {
-        "metric": "phase-space DOF-updates/sec per RK stage (FP32) + % peak HBM BW",
-        "value": value, "unit": "DOF-updates/s per RK stage", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "uneven_sweep_64", "runs": len(wls), "dof": dof, "storage": "f32",
-                   "layout_1d2v": args.layout or "vpad",
-                   "reductions": "f64", "parallelism": "single GPU, one persistent launch per stage"},
-        "hbm_effective_frac_whole_step": alg_bytes * args.steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-        "solo_sequential": {"ms_per_step": ms_solo / args.steps,
-                            "value": dof * 3 * args.steps / (ms_solo / 1e3)},
+    rec = {
+        "workload": "uneven_sweep_64", "runs": len(wls), "dof": dof, "steps": steps, "warmup": warmup,
+        "ms_per_step": ms / steps, "value": dof * 3 * steps / (ms / 1e3), "unit": "DOF-updates/s per RK stage",
+        "hbm_effective_frac_whole_step": alg_bytes * steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "solo_sequential": {"ms_per_step": ms_solo / steps, "value": dof * 3 * steps / (ms_solo / 1e3)},
         "batch_speedup_vs_solo": ms_solo / ms,
-        "tune": {"grid": b.grid, "best_ms_per_step": tuned_ms},
+        "tune": {"seconds": t_tune, "best_ms_per_step": tuned_ms, "grid": b.grid, "choice": b.choice},
     }
-    print(json.dumps(line), flush=True)
+    if bw_single:
+        rec["step_time_over_algorithmic_time_at_single_run_bw"] = (ms / steps) / (alg_bytes / (bw_single * 1e9) * 1e3)
     b.close()
     for so in solos:
         so.close()
+    return rec
+
+
+def bench_sweep(args):
+    rec = sweep_record(args.steps, args.warmup, args.layout)
+    line = {
+        "metric": "phase-space DOF-updates/sec per RK stage (FP32) + % peak HBM BW",
+        "value": rec["value"], "unit": "DOF-updates/s per RK stage", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": rec["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "uneven_sweep_64", "runs": rec["runs"], "dof": rec["dof"], "storage": "f32",
+                   "layout_1d2v": args.layout or "vpad", "reductions": "f64",
+                   "parallelism": "single GPU, persistent launches per kind and stage"},
+        "sweep": rec,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -214,6 +228,8 @@ def main():
     ap.add_argument("--layout", default=None, help="state layout: dense or vpad (1D2V only; the 1D2V default is vpad)")
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the batched 64-run sweep sub-record")
+    ap.add_argument("--sweep-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run two plain device copies of one state buffer (reference for HBM byte counters)")
     ap.add_argument("--pattern-copy", action="store_true",
@@ -320,11 +336,14 @@ def main():
         "final_mass": diag["mass"],
         "final_field_energy": diag["field_energy"],
     }
+    s.close()
+    if not args.no_sweep and wl.name == "maxwell_1d2v_n9":
+        print("[bench] batched sweep", file=sys.stderr, flush=True)
+        line["sweep"] = sweep_record(args.sweep_steps, 10, None, achieved)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)
-    s.close()
 
 
 if __name__ == "__main__":

@@ -266,22 +266,37 @@ dg_status dg_batch_destroy(dg_batch* b);
 
 /* Advance every run r by nsteps SSP-RK3 steps of its own dt[r] (host array)
  * on its state f[r] (host array of device pointers): per RK stage one
- * persistent launch per kind (n, nv) present, covering all runs of that kind,
+ * persistent launch per kind (n, nv) present, covering all runs of that kind
+ * (one after another, or as parallel graph branches, as dg_batch_tune chose),
  * then one batched field launch pair for all runs, replayed from a captured
  * HIP graph.  CFL and finiteness checks per run as
  * dg_rk_step.  host_diag: NULL or nruns*nsteps records, run-major
  * (record s of run r at host_diag[r*nsteps + s]); then the call waits.      */
 dg_status dg_batch_rk_step(dg_batch* b, void* const* f, const double* dt, int32_t nsteps, dg_diag* host_diag);
 
-/* Autotuner: time `reps` batched steps for each candidate persistent grid
- * (work-groups per CU from 1 to each kind's occupancy limit) and work-list
- * order (cost-sorted or run-interleaved), keep the fastest for this batch,
- * and return its mean step time in ms.  The states are advanced by the timed
+/* Autotuner: time `reps` batched steps per candidate and keep the fastest
+ * for this batch: first the work-list order (cost-sorted or run-interleaved)
+ * together with the kinds' launches either one after another or as parallel
+ * branches of the step graph (each kind on its own stream, forked from and
+ * joined back into the batch stream), then, per kind (n, nv), its persistent
+ * grid (work-groups per CU from 1 to the kind's occupancy limit), one kind at
+ * a time, largest first.  The per-kind grids are kept per (GPU arch, n, nv,
+ * FP32) for the life of the process and start later batches.  Returns the
+ * mean step time in ms of the choice; the states are advanced by the timed
  * steps.                                                                    */
 dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t reps, double* best_ms);
 
 /* Current persistent grid: work-groups of all kinds' stage launches summed.  */
 int32_t dg_batch_grid(const dg_batch* b);
+
+/* The current choices: returns the number of kinds K; if host_out != NULL it
+ * receives 2 + 4 K ints: [concurrent (0/1), order (0 cost-sorted, 1
+ * run-interleaved), then per kind n, nv, work-groups per CU, grid].         */
+int32_t dg_batch_choice(const dg_batch* b, int32_t* host_out);
+/* Apply choices in the layout dg_batch_choice returns (nint = 2 + 4 K; the
+ * kinds must be this batch's, in its order; the grid entries are ignored and
+ * recomputed), e.g. a tuning saved from another process.  Waits.          */
+dg_status dg_batch_set_choice(dg_batch* b, const int32_t* choice, int32_t nint);
 
 const char* dg_batch_last_error(const dg_batch* b);
 

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstring>
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -963,6 +964,26 @@ double dg_courant_number(int32_t n) {
 // Batches: every run keeps its own tables in a sub-workspace; the stage
 // kernels of all runs share one persistent launch per RK stage.
 // ---------------------------------------------------------------------------
+namespace {
+// Tuned work-groups per CU of the batched stage kernel, per (arch, n, nv,
+// FP32 storage), kept for the life of the process: later batches on the same
+// kind of GPU start from them.
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+std::string tune_key(const std::string& arch, int n, int nv) {
+  return arch + "/n" + std::to_string(n) + "/nv" + std::to_string(nv) + "/f32";
+}
+int tune_cache_get(const std::string& arch, int n, int nv, int fallback) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune_cache.find(tune_key(arch, n, nv));
+  return it == g_tune_cache.end() ? fallback : it->second;
+}
+void tune_cache_put(const std::string& arch, int n, int nv, int wm) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[tune_key(arch, n, nv)] = wm;
+}
+}  // namespace
+
 struct dg_batch {
   int nruns = 0;
   std::vector<dg_ctx*> runs;
@@ -980,9 +1001,14 @@ struct dg_batch {
   // runs of one kind (n, nv): items [begin, begin + count) of the work list
   struct Group {
     int n, nv, begin, count, occ[2], grid;
+    int wm;                                   // work-groups per CU of this kind's launch (capped by occupancy)
   };
   std::vector<Group> groups;
-  int cus = 0, wmul = 0;                      // work-groups per CU of every launch (capped by occupancy)
+  int cus = 0;
+  std::string arch;
+  bool concurrent = false;                    // kinds' launches as parallel branches of the step graph
+  std::vector<hipStream_t> kstreams;          // one per kind (concurrent form)
+  std::vector<hipEvent_t> kev;                // 3 fork + 3 * kinds join events
   std::vector<int2> items_cost, items_rr;     // the two work-list orders
   int order = 0;                              // 0: cost-sorted, 1: run-interleaved
   hipGraphExec_t gexec = nullptr;
@@ -1066,7 +1092,7 @@ dg_status upload_items(dg_batch* b) {
     xcd.insert(xcd.end(), x.begin(), x.end());
     const int occ = std::max(1, std::min(g.occ[0], g.occ[1]));
     // at least one work-group per XCD range (8), else a range would be skipped
-    g.grid = std::max(8, std::min(g.count, b->cus * std::min(b->wmul, occ)));
+    g.grid = std::max(8, std::min(g.count, b->cus * std::min(g.wm, occ)));
   }
   DGB_HIP(b, hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
   DGB_HIP(b, hipMemcpyAsync(b->d_xcd, xcd.data(), xcd.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
@@ -1104,11 +1130,23 @@ dg_status upload_args(dg_batch* b, void* const* f, const double* dt) {
 }
 
 dg_status enqueue_batch_step(dg_batch* b, bool diag) {
+  const size_t nk = b->groups.size();
   for (int k = 0; k < 3; ++k) {
-    for (size_t q = 0; q < b->groups.size(); ++q) {
+    // concurrent form: every kind's launch on its own stream, forked from and
+    // joined back into the batch stream (parallel branches of the graph)
+    const bool conc = b->concurrent && nk > 1;
+    if (conc) DGB_HIP(b, hipEventRecord(b->kev[k], b->stream));
+    for (size_t q = 0; q < nk; ++q) {
       const auto& g = b->groups[q];
+      hipStream_t st = conc ? b->kstreams[q] : b->stream;
+      if (conc) DGB_HIP(b, hipStreamWaitEvent(st, b->kev[k], 0));
       DGB_HIP(b, dgk::launch_stage_batched(k > 0, g.n, g.nv, b->d_args + k * b->nruns, b->d_items + g.begin,
-                                           b->d_xcd + 9 * q, g.grid, b->stream));
+                                           b->d_xcd + 9 * q, g.grid, st));
+      if (conc) {
+        hipEvent_t j = b->kev[3 + k * nk + q];
+        DGB_HIP(b, hipEventRecord(j, st));
+        DGB_HIP(b, hipStreamWaitEvent(b->stream, j, 0));
+      }
     }
     DGB_HIP(b, dgk::launch_field_batched(b->d_fa + k * b->nruns, b->d_xitems, b->nxitems, b->nruns, b->max_pmax, b->stream));
   }
@@ -1231,6 +1269,8 @@ dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, s
   b->run_off = BL.run_off;
   auto cleanup = [&](dg_status s, const std::string& m) {
     for (dg_ctx* c : b->runs) delete c;
+    for (hipStream_t k : b->kstreams) (void)hipStreamDestroy(k);
+    for (hipEvent_t k : b->kev) (void)hipEventDestroy(k);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -1258,6 +1298,7 @@ dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, s
   if ((e = hipGetDevice(&dev)) != hipSuccess || (e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
     return cleanup(DG_ERR_DEVICE, std::string("device query: ") + hipGetErrorString(e));
   b->cus = prop.multiProcessorCount;
+  b->arch = prop.gcnArchName;
   // Kinds in order of decreasing n.  Within a kind: runs by decreasing tile
   // cost, tiles in order (cost-sorted), or the kind's runs' tiles interleaved
   // round-robin (run-interleaved).
@@ -1300,9 +1341,21 @@ dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, s
     g.occ[0] = dgk::batched_occupancy(false, g.n, g.nv);
     g.occ[1] = dgk::batched_occupancy(true, g.n, g.nv);
     maxocc = std::max(maxocc, std::min(g.occ[0], g.occ[1]));
+    // a tuned choice for this (arch, n, nv, FP32) if one was made in this process
+    g.wm = tune_cache_get(b->arch, g.n, g.nv, std::max(1, std::min(g.occ[0], g.occ[1])));
     b->groups.push_back(g);
   }
-  b->wmul = maxocc;
+  (void)maxocc;
+  for (size_t q = 0; q < b->groups.size(); ++q) {
+    hipStream_t st = nullptr;
+    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return cleanup(DG_ERR_DEVICE, "hipStreamCreate");
+    b->kstreams.push_back(st);
+  }
+  for (size_t q = 0; q < 3 + 3 * b->groups.size(); ++q) {
+    hipEvent_t ev = nullptr;
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return cleanup(DG_ERR_DEVICE, "hipEventCreate");
+    b->kev.push_back(ev);
+  }
   b->nitems = static_cast<int>(b->items_cost.size());
   b->nxitems = static_cast<int>(xitems.size());
   if ((e = hipMemcpyAsync(b->d_xitems, xitems.data(), xitems.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream)) != hipSuccess)
@@ -1317,6 +1370,8 @@ dg_status dg_batch_destroy(dg_batch* b) {
   hipError_t e = hipStreamSynchronize(b->stream);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   for (dg_ctx* c : b->runs) (void)dg_destroy(c);
+  for (hipStream_t k : b->kstreams) (void)hipStreamDestroy(k);
+  for (hipEvent_t k : b->kev) (void)hipEventDestroy(k);
   (void)hipEventDestroy(b->ev_in);
   (void)hipEventDestroy(b->ev_out);
   (void)hipStreamDestroy(b->stream);
@@ -1379,42 +1434,71 @@ dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t r
   hipEvent_t e0, e1;
   DGB_HIP(b, hipEventCreate(&e0));
   DGB_HIP(b, hipEventCreate(&e1));
-  int occ = 1;
-  for (const auto& g : b->groups) occ = std::max(occ, std::min(g.occ[0], g.occ[1]));
-  double best = 1e300;
-  int best_w = b->wmul, best_order = b->order;
-  for (int order = 0; order < 2 && s == DG_OK; ++order) {
-    b->order = order;
-    for (int w = 1; w <= occ && s == DG_OK; ++w) {
-      b->wmul = w;
-      s = upload_items(b);
-      if (s != DG_OK) break;
-      if (b->gexec) {
-        (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
-      }
-      s = build_batch_graph(b, f, dt, false);
-      if (s != DG_OK) break;
-      DGB_HIP(b, hipGraphLaunch(b->gexec, b->stream));   // warm-up
-      DGB_HIP(b, hipEventRecord(e0, b->stream));
-      for (int k = 0; k < reps; ++k) DGB_HIP(b, hipGraphLaunch(b->gexec, b->stream));
-      DGB_HIP(b, hipEventRecord(e1, b->stream));
-      DGB_HIP(b, hipEventSynchronize(e1));
-      float ms = 0.0f;
-      DGB_HIP(b, hipEventElapsedTime(&ms, e0, e1));
-      if (ms / reps < best) {
-        best = ms / reps;
-        best_w = w;
-        best_order = order;
-      }
-      for (int r = 0; r < b->nruns; ++r) b->runs[r]->t += (reps + 1) * dt[r];
+  // mean ms per step of the current choices (graph rebuilt, one warm-up replay)
+  auto measure = [&](double* ms_out) -> dg_status {
+    dg_status st = upload_items(b);
+    if (st != DG_OK) return st;
+    if (b->gexec) {
+      (void)hipGraphExecDestroy(b->gexec);
+      b->gexec = nullptr;
     }
+    st = build_batch_graph(b, f, dt, false);
+    if (st != DG_OK) return st;
+    DGB_HIP(b, hipGraphLaunch(b->gexec, b->stream));
+    DGB_HIP(b, hipEventRecord(e0, b->stream));
+    for (int k = 0; k < reps; ++k) DGB_HIP(b, hipGraphLaunch(b->gexec, b->stream));
+    DGB_HIP(b, hipEventRecord(e1, b->stream));
+    DGB_HIP(b, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    DGB_HIP(b, hipEventElapsedTime(&ms, e0, e1));
+    for (int r = 0; r < b->nruns; ++r) b->runs[r]->t += (reps + 1) * dt[r];
+    *ms_out = ms / reps;
+    return DG_OK;
+  };
+  auto occ_of = [](const dg_batch::Group& g) { return std::max(1, std::min(g.occ[0], g.occ[1])); };
+  // 1. list order x kind concurrency, every kind at its occupancy limit
+  for (auto& g : b->groups) g.wm = occ_of(g);
+  double best = 1e300;
+  int best_order = b->order;
+  bool best_conc = b->concurrent;
+  for (int conc = 0; conc < 2 && s == DG_OK; ++conc)
+    for (int order = 0; order < 2 && s == DG_OK; ++order) {
+      b->concurrent = conc != 0;
+      b->order = order;
+      double ms = 0.0;
+      s = measure(&ms);
+      if (s == DG_OK && ms < best) {
+        best = ms;
+        best_order = order;
+        best_conc = b->concurrent;
+      }
+    }
+  b->order = best_order;
+  b->concurrent = best_conc;
+  // 2. per kind (n, nv): its work-groups per CU, one kind at a time with the
+  //    others at their current best (coordinate descent, largest kinds first)
+  std::vector<size_t> byc(b->groups.size());
+  for (size_t q = 0; q < byc.size(); ++q) byc[q] = q;
+  std::stable_sort(byc.begin(), byc.end(), [&](size_t p, size_t q) { return b->groups[p].count > b->groups[q].count; });
+  for (size_t q : byc) {
+    if (s != DG_OK) break;
+    auto& g = b->groups[q];
+    int best_w = g.wm;
+    for (int w = 1; w < occ_of(g) && s == DG_OK; ++w) {
+      g.wm = w;
+      double ms = 0.0;
+      s = measure(&ms);
+      if (s == DG_OK && ms < best) {
+        best = ms;
+        best_w = w;
+      }
+    }
+    g.wm = best_w;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (s != DG_OK) return s;
-  b->wmul = best_w;
-  b->order = best_order;
+  for (const auto& g : b->groups) tune_cache_put(b->arch, g.n, g.nv, g.wm);
   s = upload_items(b);
   if (s != DG_OK) return s;
   if (b->gexec) {
@@ -1423,6 +1507,44 @@ dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t r
   }
   if (best_ms) *best_ms = best;
   return batch_leave(b);
+}
+
+int32_t dg_batch_choice(const dg_batch* b, int32_t* host_out) {
+  if (!b) return 0;
+  const int nk = static_cast<int>(b->groups.size());
+  if (host_out) {
+    host_out[0] = b->concurrent ? 1 : 0;
+    host_out[1] = b->order;
+    for (int q = 0; q < nk; ++q) {
+      host_out[2 + 4 * q] = b->groups[q].n;
+      host_out[3 + 4 * q] = b->groups[q].nv;
+      host_out[4 + 4 * q] = b->groups[q].wm;
+      host_out[5 + 4 * q] = b->groups[q].grid;
+    }
+  }
+  return nk;
+}
+
+dg_status dg_batch_set_choice(dg_batch* b, const int32_t* choice, int32_t nint) {
+  if (!b) return DG_ERR_INVALID;
+  const int nk = static_cast<int>(b->groups.size());
+  if (!choice || nint != 2 + 4 * nk) return bfail(b, DG_ERR_INVALID, "dg_batch_set_choice: need 2 + 4 * kinds ints");
+  if ((choice[0] != 0 && choice[0] != 1) || (choice[1] != 0 && choice[1] != 1))
+    return bfail(b, DG_ERR_INVALID, "dg_batch_set_choice: concurrent and order must be 0 or 1");
+  for (int q = 0; q < nk; ++q) {
+    const auto& g = b->groups[q];
+    if (choice[2 + 4 * q] != g.n || choice[3 + 4 * q] != g.nv)
+      return bfail(b, DG_ERR_INVALID, "dg_batch_set_choice: kinds differ from this batch's");
+    if (choice[4 + 4 * q] < 1) return bfail(b, DG_ERR_INVALID, "dg_batch_set_choice: work-groups per CU must be >= 1");
+  }
+  b->concurrent = choice[0] != 0;
+  b->order = choice[1];
+  for (int q = 0; q < nk; ++q) b->groups[q].wm = choice[4 + 4 * q];
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  return upload_items(b);
 }
 
 int32_t dg_batch_grid(const dg_batch* b) {

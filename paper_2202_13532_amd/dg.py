@@ -28,7 +28,7 @@ EXPORTED = ["dg_workspace_bytes", "dg_init", "dg_destroy", "dg_rhs", "dg_poisson
             "dg_projection_matrix", "dg_project", "dg_nn_features", "dg_nn_features_raw", "dg_nn_to_elements",
             "dg_nn_column_stats", "dg_nn_rk_step", "dg_nn_last_error", "dg_state_elems", "dg_state_pack",
             "dg_state_unpack", "dg_rhs_static", "dg_set_background", "dg_fourier", "dg_filter_x",
-            "dg_profile_copy"]
+            "dg_profile_copy", "dg_batch_choice", "dg_batch_set_choice"]
 
 
 class dg_config(ctypes.Structure):
@@ -118,6 +118,8 @@ def lib():
         "dg_fourier": (I, [P, P, P]),
         "dg_filter_x": (I, [P, dp, P, P]),
         "dg_profile_copy": (I, [P, P, P, I, I, dp]),
+        "dg_batch_choice": (I, [P, ip]),
+        "dg_batch_set_choice": (I, [P, ip, I]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -480,6 +482,25 @@ def dg_batch_grid(b):
     return int(lib().dg_batch_grid(b))
 
 
+def dg_batch_choice(b):
+    k = int(lib().dg_batch_choice(b, None))
+    out = (ctypes.c_int32 * (2 + 4 * k))()
+    lib().dg_batch_choice(b, out)
+    kinds = [{"n": out[2 + 4 * q], "nv": out[3 + 4 * q], "wg_per_cu": out[4 + 4 * q], "grid": out[5 + 4 * q]}
+             for q in range(k)]
+    return {"concurrent": bool(out[0]), "order": "run-interleaved" if out[1] else "cost-sorted", "kinds": kinds}
+
+
+def dg_batch_set_choice(b, choice):
+    k = len(choice["kinds"])
+    arr = (ctypes.c_int32 * (2 + 4 * k))()
+    arr[0] = 1 if choice["concurrent"] else 0
+    arr[1] = 1 if choice["order"] == "run-interleaved" else 0
+    for q, kd in enumerate(choice["kinds"]):
+        arr[2 + 4 * q], arr[3 + 4 * q], arr[4 + 4 * q], arr[5 + 4 * q] = kd["n"], kd["nv"], kd["wg_per_cu"], 0
+    _bcheck(lib().dg_batch_set_choice(b, arr, 2 + 4 * k), b)
+
+
 class Batch:
     """Many independent runs stepped by one persistent launch per RK stage."""
 
@@ -526,6 +547,14 @@ class Batch:
     @property
     def grid(self):
         return dg_batch_grid(self.b)
+
+    @property
+    def choice(self):
+        return dg_batch_choice(self.b)
+
+    @choice.setter
+    def choice(self, c):
+        dg_batch_set_choice(self.b, c)
 
 
 # ---------------- learned coarse-grid correction ----------------

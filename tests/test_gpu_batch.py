@@ -125,3 +125,43 @@ def test_uneven_sweep_64_runs_conserves_mass():
         assert r[-1]["finite"] == 1
         assert abs(r[-1]["mass"] - r[0]["mass"]) < 1e-6 * abs(r[0]["mass"]), w.name
     B.close()
+
+
+def test_batch_launch_forms_and_tuner_keep_bitwise_equality():
+    """Serial and concurrent kind launches, any per-kind grid, and the tuner's
+    choice all give the solo runs' results bit for bit."""
+    cases = SMALL
+    cfgs = [dg.make_config(*c[:6]) for c in cases]
+    B = dg.Batch(cfgs)
+    solos = [dg.Solver(*c[:6]) for c in cases]
+    init = [torch.from_numpy(_state(c, 10 + i)[1]).float().cuda() for i, c in enumerate(cases)]
+    dts = [0.4 * so.dt_max(0.2) for so in solos]
+    ref = [f.clone() for f in init]
+    for so, f, dt in zip(solos, ref, dts):
+        so.step(f, dt, 2)
+    base = B.choice
+    assert len(base["kinds"]) == len({(c[1], c[0]) for c in cases})
+    for conc in (False, True):
+        for order in ("cost-sorted", "run-interleaved"):
+            ch = {"concurrent": conc, "order": order,
+                  "kinds": [dict(k, wg_per_cu=1 + (i % 2)) for i, k in enumerate(base["kinds"])]}
+            B.choice = ch
+            got = B.choice
+            assert got["concurrent"] == conc and got["order"] == order
+            states = [f.clone() for f in init]
+            B.step(states, dts, 2)
+            for a, b in zip(states, ref):
+                assert torch.equal(a, b), (conc, order)
+    # the tuner (states advance during tuning: tune on copies)
+    scratch = [f.clone() for f in init]
+    ms = B.tune(scratch, dts, 1)
+    assert ms > 0
+    states = [f.clone() for f in init]
+    B.step(states, dts, 2)
+    for a, b in zip(states, ref):
+        assert torch.equal(a, b)
+    with pytest.raises(dg.DGError):
+        B.choice = {"concurrent": True, "order": "cost-sorted", "kinds": base["kinds"][:-1]}
+    B.close()
+    for so in solos:
+        so.close()

@@ -16,7 +16,14 @@ The JSON line also carries
                    (dg_profile_step), against 8 TB/s; traffic from the committed
                    rocprofv3 counter summary when it matches the kernel source.
   cpu_baseline  -- the FP64 NumPy oracle timed on the host on a bounded sample
-                   (one RK stage on a 1/8 x-subdomain with halo).
+                   (one RK stage on a 1/8 x-subdomain with halo), plus one RHS
+                   and one RK3 step on the 1D1V Landau and 16.8 M DOF ring
+                   workloads and the CPU model.
+  fp64_storage  -- the same workload in FP64 storage (--no-fp64 skips it).
+  sweep         -- the batched 64-run uneven sweep under the tuner's choice,
+                   against its solo runs (--no-sweep skips it).
+--pattern-copy prints the copy references instead (streaming and tile-pattern
+copies of one state buffer next to the stage kernels).
 """
 import argparse
 import hashlib
@@ -203,6 +210,33 @@ def sweep_record(steps, warmup, layout=None, bw_single=None):
     return rec
 
 
+def fp64_record(torch, dg, wl, layout, steps, warmup=10):
+    """The same workload in FP64 storage (the precision of the paper's code):
+    graph-replayed steps and the stage kernels' HIP-event durations."""
+    s = dg.Solver(wl.nv, wl.n, wl.nelem, wl.lo, wl.hi, wl.omega_c, 0, "f64", layout=layout)
+    f = make_state(torch, s, wl)
+    E0 = s.poisson(f)
+    dt = wl.cfl_fraction * s.dt_max(max(float(E0.abs().max()), 0.05))
+    s.step(f, dt, warmup)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    s.step(f, dt, steps)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    prof = s.profile_step(f, dt, 2)
+    st_ms = prof[:, [0, 2, 4]].mean(axis=0)
+    dof = wl.dof()
+    byts = [16 * dof, 24 * dof, 24 * dof]
+    achieved = sum(byts) / (st_ms.sum() / 1e3) / 1e9
+    s.close()
+    return {"steps": steps, "warmup": warmup, "ms_per_step": ms / steps,
+            "value": dof * 3 * steps / (ms / 1e3), "unit": "DOF-updates/s per RK stage",
+            "stage_ms_mean": [float(x) for x in st_ms], "algorithmic_GBs": achieved,
+            "frac": achieved / HBM_PEAK_GBS}
+
+
 def bench_sweep(args):
     rec = sweep_record(args.steps, args.warmup, args.layout)
     line = {
@@ -229,6 +263,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched 64-run sweep sub-record")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage sub-record")
+    ap.add_argument("--fp64-steps", type=int, default=20)
     ap.add_argument("--sweep-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run two plain device copies of one state buffer (reference for HBM byte counters)")
@@ -337,6 +373,9 @@ def main():
         "final_field_energy": diag["field_energy"],
     }
     s.close()
+    if not args.no_fp64 and wl.name == "maxwell_1d2v_n9" and wl.storage == "f32":
+        print("[bench] FP64 storage, same workload", file=sys.stderr, flush=True)
+        line["fp64_storage"] = fp64_record(torch, dg, wl, layout, args.fp64_steps)
     if not args.no_sweep and wl.name == "maxwell_1d2v_n9":
         print("[bench] batched sweep", file=sys.stderr, flush=True)
         line["sweep"] = sweep_record(args.sweep_steps, 10, None, achieved)

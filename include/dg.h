@@ -266,8 +266,7 @@ dg_status dg_batch_destroy(dg_batch* b);
 
 /* Advance every run r by nsteps SSP-RK3 steps of its own dt[r] (host array)
  * on its state f[r] (host array of device pointers): per RK stage one
- * persistent launch per kind (n, nv) present, covering all runs of that kind
- * (one after another, or as parallel graph branches, as dg_batch_tune chose),
+ * persistent launch per kind (n, nv) present, covering all runs of that kind,
  * then one batched field launch pair for all runs, replayed from a captured
  * HIP graph.  CFL and finiteness checks per run as
  * dg_rk_step.  host_diag: NULL or nruns*nsteps records, run-major
@@ -275,12 +274,9 @@ dg_status dg_batch_destroy(dg_batch* b);
 dg_status dg_batch_rk_step(dg_batch* b, void* const* f, const double* dt, int32_t nsteps, dg_diag* host_diag);
 
 /* Autotuner: time `reps` batched steps per candidate and keep the fastest
- * for this batch: first the work-list order (cost-sorted or run-interleaved)
- * together with the kinds' launches either one after another or as parallel
- * branches of the step graph (each kind on its own stream, forked from and
- * joined back into the batch stream), then, per kind (n, nv), its persistent
- * grid (work-groups per CU from 1 to the kind's occupancy limit), one kind at
- * a time, largest first.  The per-kind grids are kept per (GPU arch, n, nv,
+ * for this batch: first the work-list order (cost-sorted or run-interleaved),
+ * then, per kind (n, nv), its persistent grid (work-groups per CU from 1 to
+ * the kind's occupancy limit), one kind at a time, largest first.  The per-kind grids are kept per (GPU arch, n, nv,
  * FP32) for the life of the process and start later batches.  Returns the
  * mean step time in ms of the choice; the states are advanced by the timed
  * steps.                                                                    */
@@ -290,12 +286,14 @@ dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t r
 int32_t dg_batch_grid(const dg_batch* b);
 
 /* The current choices: returns the number of kinds K; if host_out != NULL it
- * receives 2 + 4 K ints: [concurrent (0/1), order (0 cost-sorted, 1
- * run-interleaved), then per kind n, nv, work-groups per CU, grid].         */
+ * receives 2 + 4 K ints: [concurrent kind launches (always 0: the form is
+ * switched off), order (0 cost-sorted, 1 run-interleaved), then per kind n,
+ * nv, work-groups per CU, grid].                                            */
 int32_t dg_batch_choice(const dg_batch* b, int32_t* host_out);
 /* Apply choices in the layout dg_batch_choice returns (nint = 2 + 4 K; the
  * kinds must be this batch's, in its order; the grid entries are ignored and
- * recomputed), e.g. a tuning saved from another process.  Waits.          */
+ * recomputed), e.g. a tuning saved from another process.  Concurrent kind
+ * launches (first entry 1) return DG_ERR_UNSUPPORTED.  Waits.             */
 dg_status dg_batch_set_choice(dg_batch* b, const int32_t* choice, int32_t nint);
 
 const char* dg_batch_last_error(const dg_batch* b);

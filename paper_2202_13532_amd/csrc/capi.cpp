@@ -1006,9 +1006,6 @@ struct dg_batch {
   std::vector<Group> groups;
   int cus = 0;
   std::string arch;
-  bool concurrent = false;                    // kinds' launches as parallel branches of the step graph
-  std::vector<hipStream_t> kstreams;          // one per kind (concurrent form)
-  std::vector<hipEvent_t> kev;                // 3 fork + 3 * kinds join events
   std::vector<int2> items_cost, items_rr;     // the two work-list orders
   int order = 0;                              // 0: cost-sorted, 1: run-interleaved
   hipGraphExec_t gexec = nullptr;
@@ -1132,21 +1129,10 @@ dg_status upload_args(dg_batch* b, void* const* f, const double* dt) {
 dg_status enqueue_batch_step(dg_batch* b, bool diag) {
   const size_t nk = b->groups.size();
   for (int k = 0; k < 3; ++k) {
-    // concurrent form: every kind's launch on its own stream, forked from and
-    // joined back into the batch stream (parallel branches of the graph)
-    const bool conc = b->concurrent && nk > 1;
-    if (conc) DGB_HIP(b, hipEventRecord(b->kev[k], b->stream));
     for (size_t q = 0; q < nk; ++q) {
       const auto& g = b->groups[q];
-      hipStream_t st = conc ? b->kstreams[q] : b->stream;
-      if (conc) DGB_HIP(b, hipStreamWaitEvent(st, b->kev[k], 0));
       DGB_HIP(b, dgk::launch_stage_batched(k > 0, g.n, g.nv, b->d_args + k * b->nruns, b->d_items + g.begin,
-                                           b->d_xcd + 9 * q, g.grid, st));
-      if (conc) {
-        hipEvent_t j = b->kev[3 + k * nk + q];
-        DGB_HIP(b, hipEventRecord(j, st));
-        DGB_HIP(b, hipStreamWaitEvent(b->stream, j, 0));
-      }
+                                           b->d_xcd + 9 * q, g.grid, b->stream));
     }
     DGB_HIP(b, dgk::launch_field_batched(b->d_fa + k * b->nruns, b->d_xitems, b->nxitems, b->nruns, b->max_pmax, b->stream));
   }
@@ -1269,8 +1255,6 @@ dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, s
   b->run_off = BL.run_off;
   auto cleanup = [&](dg_status s, const std::string& m) {
     for (dg_ctx* c : b->runs) delete c;
-    for (hipStream_t k : b->kstreams) (void)hipStreamDestroy(k);
-    for (hipEvent_t k : b->kev) (void)hipEventDestroy(k);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -1346,16 +1330,6 @@ dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, s
     b->groups.push_back(g);
   }
   (void)maxocc;
-  for (size_t q = 0; q < b->groups.size(); ++q) {
-    hipStream_t st = nullptr;
-    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return cleanup(DG_ERR_DEVICE, "hipStreamCreate");
-    b->kstreams.push_back(st);
-  }
-  for (size_t q = 0; q < 3 + 3 * b->groups.size(); ++q) {
-    hipEvent_t ev = nullptr;
-    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return cleanup(DG_ERR_DEVICE, "hipEventCreate");
-    b->kev.push_back(ev);
-  }
   b->nitems = static_cast<int>(b->items_cost.size());
   b->nxitems = static_cast<int>(xitems.size());
   if ((e = hipMemcpyAsync(b->d_xitems, xitems.data(), xitems.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream)) != hipSuccess)
@@ -1370,8 +1344,6 @@ dg_status dg_batch_destroy(dg_batch* b) {
   hipError_t e = hipStreamSynchronize(b->stream);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   for (dg_ctx* c : b->runs) (void)dg_destroy(c);
-  for (hipStream_t k : b->kstreams) (void)hipStreamDestroy(k);
-  for (hipEvent_t k : b->kev) (void)hipEventDestroy(k);
   (void)hipEventDestroy(b->ev_in);
   (void)hipEventDestroy(b->ev_out);
   (void)hipStreamDestroy(b->stream);
@@ -1456,25 +1428,20 @@ dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t r
     return DG_OK;
   };
   auto occ_of = [](const dg_batch::Group& g) { return std::max(1, std::min(g.occ[0], g.occ[1])); };
-  // 1. list order x kind concurrency, every kind at its occupancy limit
+  // 1. list order, every kind at its occupancy limit
   for (auto& g : b->groups) g.wm = occ_of(g);
   double best = 1e300;
   int best_order = b->order;
-  bool best_conc = b->concurrent;
-  for (int conc = 0; conc < 2 && s == DG_OK; ++conc)
-    for (int order = 0; order < 2 && s == DG_OK; ++order) {
-      b->concurrent = conc != 0;
-      b->order = order;
-      double ms = 0.0;
-      s = measure(&ms);
-      if (s == DG_OK && ms < best) {
-        best = ms;
-        best_order = order;
-        best_conc = b->concurrent;
-      }
+  for (int order = 0; order < 2 && s == DG_OK; ++order) {
+    b->order = order;
+    double ms = 0.0;
+    s = measure(&ms);
+    if (s == DG_OK && ms < best) {
+      best = ms;
+      best_order = order;
     }
+  }
   b->order = best_order;
-  b->concurrent = best_conc;
   // 2. per kind (n, nv): its work-groups per CU, one kind at a time with the
   //    others at their current best (coordinate descent, largest kinds first)
   std::vector<size_t> byc(b->groups.size());
@@ -1513,7 +1480,7 @@ int32_t dg_batch_choice(const dg_batch* b, int32_t* host_out) {
   if (!b) return 0;
   const int nk = static_cast<int>(b->groups.size());
   if (host_out) {
-    host_out[0] = b->concurrent ? 1 : 0;
+    host_out[0] = 0;   // kinds' launches one after another
     host_out[1] = b->order;
     for (int q = 0; q < nk; ++q) {
       host_out[2 + 4 * q] = b->groups[q].n;
@@ -1529,7 +1496,9 @@ dg_status dg_batch_set_choice(dg_batch* b, const int32_t* choice, int32_t nint) 
   if (!b) return DG_ERR_INVALID;
   const int nk = static_cast<int>(b->groups.size());
   if (!choice || nint != 2 + 4 * nk) return bfail(b, DG_ERR_INVALID, "dg_batch_set_choice: need 2 + 4 * kinds ints");
-  if ((choice[0] != 0 && choice[0] != 1) || (choice[1] != 0 && choice[1] != 1))
+  if (choice[0] == 1)
+    return bfail(b, DG_ERR_UNSUPPORTED, "dg_batch_set_choice: concurrent kind launches are switched off");
+  if (choice[0] != 0 || (choice[1] != 0 && choice[1] != 1))
     return bfail(b, DG_ERR_INVALID, "dg_batch_set_choice: concurrent and order must be 0 or 1");
   for (int q = 0; q < nk; ++q) {
     const auto& g = b->groups[q];
@@ -1537,7 +1506,6 @@ dg_status dg_batch_set_choice(dg_batch* b, const int32_t* choice, int32_t nint) 
       return bfail(b, DG_ERR_INVALID, "dg_batch_set_choice: kinds differ from this batch's");
     if (choice[4 + 4 * q] < 1) return bfail(b, DG_ERR_INVALID, "dg_batch_set_choice: work-groups per CU must be >= 1");
   }
-  b->concurrent = choice[0] != 0;
   b->order = choice[1];
   for (int q = 0; q < nk; ++q) b->groups[q].wm = choice[4 + 4 * q];
   if (b->gexec) {

@@ -127,9 +127,7 @@ def test_uneven_sweep_64_runs_conserves_mass():
     B.close()
 
 
-def test_batch_launch_forms_and_tuner_keep_bitwise_equality():
-    """Serial and concurrent kind launches, any per-kind grid, and the tuner's
-    choice all give the solo runs' results bit for bit."""
+def _launch_form_check(concurrent_forms):
     cases = SMALL
     cfgs = [dg.make_config(*c[:6]) for c in cases]
     B = dg.Batch(cfgs)
@@ -141,7 +139,7 @@ def test_batch_launch_forms_and_tuner_keep_bitwise_equality():
         so.step(f, dt, 2)
     base = B.choice
     assert len(base["kinds"]) == len({(c[1], c[0]) for c in cases})
-    for conc in (False, True):
+    for conc in concurrent_forms:
         for order in ("cost-sorted", "run-interleaved"):
             ch = {"concurrent": conc, "order": order,
                   "kinds": [dict(k, wg_per_cu=1 + (i % 2)) for i, k in enumerate(base["kinds"])]}
@@ -152,8 +150,14 @@ def test_batch_launch_forms_and_tuner_keep_bitwise_equality():
             B.step(states, dts, 2)
             for a, b in zip(states, ref):
                 assert torch.equal(a, b), (conc, order)
-    # the tuner (states advance during tuning: tune on copies)
-    scratch = [f.clone() for f in init]
+    return B, solos, init, dts, ref, base
+
+
+def test_batch_orders_grids_and_tuner_keep_bitwise_equality():
+    """Both work-list orders, any per-kind grid and the tuner's choice give
+    the solo runs' results bit for bit."""
+    B, solos, init, dts, ref, base = _launch_form_check([False])
+    scratch = [f.clone() for f in init]          # the tuner advances the states it times
     ms = B.tune(scratch, dts, 1)
     assert ms > 0
     states = [f.clone() for f in init]
@@ -161,7 +165,20 @@ def test_batch_launch_forms_and_tuner_keep_bitwise_equality():
     for a, b in zip(states, ref):
         assert torch.equal(a, b)
     with pytest.raises(dg.DGError):
-        B.choice = {"concurrent": True, "order": "cost-sorted", "kinds": base["kinds"][:-1]}
+        B.choice = dict(base, kinds=base["kinds"][:-1])
+    with pytest.raises(dg.DGError) as ex:
+        B.choice = dict(base, concurrent=True)
+    assert ex.value.status == dg.DG_ERR_UNSUPPORTED
+    B.close()
+    for so in solos:
+        so.close()
+
+
+@pytest.mark.skip(reason="concurrent kind launches (per-kind streams forked into the captured step graph) "
+                         "are switched off: a run of the tuner over that form ended in a host segmentation "
+                         "fault whose cause is not established")
+def test_batch_concurrent_kind_launches_keep_bitwise_equality():
+    B, solos, _, _, _, _ = _launch_form_check([True])
     B.close()
     for so in solos:
         so.close()

@@ -38,13 +38,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2202_13532_amd", "csrc", "dg_kernels.hip")
+# the single-run stage kernels: their launch code and the shared tile code
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_13532_amd", "csrc", f)
+                  for f in ("dg_kernels.hip", "stage_tiles.h", "dg_ops_constexpr.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_traffic.json")
 
 
 def kernel_source_hash():
-    with open(KERNEL_SOURCE, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(workload):

@@ -257,7 +257,8 @@ typedef struct dg_batch dg_batch;
 size_t dg_batch_workspace_bytes(const dg_config* cfgs, int32_t nruns);
 
 /* Set up every run (as dg_init does) inside one workspace, group the runs by
- * kind (n, nv), build each kind's (run, tile) work list ordered by
+ * kind (the 1D2V runs by n; all 1D1V runs, any n, form one kind, reported
+ * as (n, nv) = (0, 1)), build each kind's (run, tile) work list ordered by
  * decreasing tile cost and split over the 8 XCDs, and bind the batch to
  * hip_stream.  cfgs is copied.                                              */
 dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, size_t workspace_bytes,
@@ -266,7 +267,7 @@ dg_status dg_batch_destroy(dg_batch* b);
 
 /* Advance every run r by nsteps SSP-RK3 steps of its own dt[r] (host array)
  * on its state f[r] (host array of device pointers): per RK stage one
- * persistent launch per kind (n, nv) present, covering all runs of that kind,
+ * persistent launch per kind present, covering all runs of that kind,
  * then one batched field launch pair for all runs, replayed from a captured
  * HIP graph.  CFL and finiteness checks per run as
  * dg_rk_step.  host_diag: NULL or nruns*nsteps records, run-major
@@ -276,8 +277,9 @@ dg_status dg_batch_rk_step(dg_batch* b, void* const* f, const double* dt, int32_
 /* Autotuner: time `reps` batched steps per candidate and keep the fastest
  * for this batch: first the work-list order (cost-sorted or run-interleaved),
  * then, per kind (n, nv), its persistent grid (work-groups per CU from 1 to
- * the kind's occupancy limit), one kind at a time, largest first.  The per-kind grids are kept per (GPU arch, n, nv,
- * FP32) for the life of the process and start later batches.  Returns the
+ * the kind's occupancy limit), one kind at a time, largest first.  The
+ * per-kind grids are kept per (GPU arch, n, nv, FP32) for the life of the
+ * process and start later batches.  Returns the
  * mean step time in ms of the choice; the states are advanced by the timed
  * steps.                                                                    */
 dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t reps, double* best_ms);

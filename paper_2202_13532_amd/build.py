@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libdg.so")
 
-SOURCES = ["dg_kernels.hip", "nn_kernels.hip", "static_rhs.hip", "basis.cpp", "spectral.cpp", "capi.cpp",
+SOURCES = ["dg_kernels.hip", "batched_kernels.hip", "nn_kernels.hip", "static_rhs.hip", "basis.cpp", "spectral.cpp", "capi.cpp",
            "nn_capi.cpp"]
 ARCH = os.environ.get("DG_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -199,6 +199,7 @@ void fill_pack(const dg_ctx* c, dgk::StageArgs<T>* p, const void* fin, const voi
   a.lpitch = L.lpitch;
   a.nt_store = 3 * L.selems * L.esize > kLastLevelCache ? 1 : 0;
   a.zero_inflow = c->cfg.vbc == DG_VBC_ZERO_INFLOW ? 1 : 0;
+  a.n1v = c->cfg.nv == 1 ? c->cfg.n : 0;
   a.Jx = static_cast<T>(2.0 / c->dx[0]);
   if (c->cfg.nv == 2) {
     a.Ju = static_cast<T>(2.0 / c->dx[1]);
@@ -1283,13 +1284,14 @@ dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, s
     return cleanup(DG_ERR_DEVICE, std::string("device query: ") + hipGetErrorString(e));
   b->cus = prop.multiProcessorCount;
   b->arch = prop.gcnArchName;
-  // Kinds in order of decreasing n.  Within a kind: runs by decreasing tile
+  // Kinds: the 1D2V runs by n, in order of decreasing n, then all 1D1V runs
+  // (any n) as one kind (code 1).  Within a kind: runs by decreasing tile
   // cost, tiles in order (cost-sorted), or the kind's runs' tiles interleaved
   // round-robin (run-interleaved).
   std::vector<int2> xitems;
   std::vector<int> kinds;
   for (int r = 0; r < nruns; ++r) {
-    kinds.push_back(10 * cfgs[r].n + cfgs[r].nv);
+    kinds.push_back(cfgs[r].nv == 2 ? 10 * cfgs[r].n + 2 : 1);
     for (int ix = 0; ix < b->runs[r]->L.Nx; ++ix) xitems.push_back(make_int2(r, ix));
     b->max_pmax = std::max(b->max_pmax, b->runs[r]->L.pmax);
   }
@@ -1299,8 +1301,8 @@ dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, s
   int maxocc = 1;
   for (int kd : distinct) {
     dg_batch::Group g{};
-    g.n = kd / 10;
-    g.nv = kd % 10;
+    g.n = kd == 1 ? 0 : kd / 10;   // the 1D1V kind is reported as (n, nv) = (0, 1)
+    g.nv = kd == 1 ? 1 : 2;
     g.begin = static_cast<int>(b->items_cost.size());
     std::vector<int> byc;
     for (int r = 0; r < nruns; ++r)

@@ -37,6 +37,7 @@ struct StageArgs {
   int nt_store;           // 1: non-temporal stores (the run's three state buffers exceed the last-level cache)
   int reverse;            // 1: 1D2V tiles visited in reverse order (single-run stage launches)
   int zero_inflow;        // 1: zero outside the velocity box
+  int n1v;                // batched launches: n of a 1D1V run, 0 for a 1D2V run
   T Jx, Ju, Jv, wc;       // Jacobians 2/dx per axis, omega_c
   T c_un, c_in, c_dt;     // stage coefficients
 };
@@ -82,12 +83,13 @@ hipError_t launch_xfilter(bool f64, const void* in, void* out, const void* M, in
 hipError_t launch_repack(bool pack, bool f64, const void* in, void* out, size_t rows, unsigned lp, unsigned cp,
                          unsigned tvn, unsigned nvn, hipStream_t s);
 
-// Batched persistent stage of one kind (n, nv): `runs` (device) holds one
+// Batched persistent stage of one kind: `runs` (device) holds one
 // StageArgs<float> per run of the batch, `items` (device) the kind's (run,
 // tile) work list, `xcd_begin` (device, 9 entries, relative to `items`) its
-// split over the 8 XCDs.
-hipError_t launch_stage_batched(bool un, int n, int nv, const StageArgs<float>* runs, const int2* items, const int* xcd_begin,
-                                int grid, hipStream_t s);
+// split over the 8 XCDs.  nv = 2: the 1D2V runs of n nodes; nv = 1: the 1D1V
+// runs of any n (StageArgs::n1v; n ignored).
+hipError_t launch_stage_batched(bool un, int n, int nv, const StageArgs<float>* runs, const int2* items,
+                                const int* xcd_begin, int grid, hipStream_t s);
 // Batched field solve: `fa` (device) one FieldArgs per run, `xitems` (device)
 // the (run, x element) list.
 hipError_t launch_field_batched(const FieldArgs* fa, const int2* xitems, int nxitems, int nruns, int max_pmax, hipStream_t s);

@@ -127,6 +127,46 @@ def test_uneven_sweep_64_runs_conserves_mass():
     B.close()
 
 
+def _check_kinds(choice, cases):
+    """One launch per 1D2V n, in decreasing n, then one for all 1D1V runs,
+    reported as (n, nv) = (0, 1)."""
+    kinds = [(k["n"], k["nv"]) for k in choice["kinds"]]
+    want = [(n, 2) for n in sorted({c[1] for c in cases if c[0] == 2}, reverse=True)]
+    if any(c[0] == 1 for c in cases):
+        want.append((0, 1))
+    assert kinds == want
+
+
+@pytest.mark.parametrize("which", ["1d1v_only", "1d1v_with_n5", "all"])
+def test_batch_1d1v_launch_forms_bitwise_equal_to_solo(which):
+    """1D1V runs of several n share one launch: alone, next to one 1D2V kind
+    and next to several; every run equals its solo run bit for bit."""
+    if which == "1d1v_only":
+        cases = [c for c in SMALL if c[0] == 1]
+    elif which == "1d1v_with_n5":
+        cases = [c for c in SMALL if c[0] == 1 or c[1] == 5]
+    else:
+        cases = SMALL
+    print("batch launch forms", which, flush=True)
+    B = dg.Batch([dg.make_config(*c[:6]) for c in cases])
+    _check_kinds(B.choice, cases)
+    states, solo, dts, sols = [], [], [], []
+    for i, c in enumerate(cases):
+        _, f = _state(c, 40 + i)
+        states.append(torch.from_numpy(f).float().cuda())
+        solo.append(states[-1].clone())
+        sols.append(dg.Solver(*c[:6]))
+        dts.append(0.4 * sols[-1].dt_max(0.2))
+    B.step(states, dts, 2)
+    for so, f, dt in zip(sols, solo, dts):
+        so.step(f, dt, 2)
+    for i, (a, b) in enumerate(zip(states, solo)):
+        assert torch.equal(a, b), (which, i)
+    B.close()
+    for so in sols:
+        so.close()
+
+
 def _launch_form_check(concurrent_forms):
     cases = SMALL
     cfgs = [dg.make_config(*c[:6]) for c in cases]
@@ -138,7 +178,7 @@ def _launch_form_check(concurrent_forms):
     for so, f, dt in zip(solos, ref, dts):
         so.step(f, dt, 2)
     base = B.choice
-    assert len(base["kinds"]) == len({(c[1], c[0]) for c in cases})
+    _check_kinds(base, cases)
     for conc in concurrent_forms:
         for order in ("cost-sorted", "run-interleaved"):
             ch = {"concurrent": conc, "order": order,

@@ -257,6 +257,59 @@ def bench_sweep(args):
     print(json.dumps(line), flush=True)
 
 
+def write_traffic(fetch_dir, write_dir, workload="maxwell_1d2v_n9"):
+    """Summarise two rocprofv3 counter runs of `bench.py --copy-calibration`
+    (one with FETCH_SIZE, one with WRITE_SIZE; their output directories) into
+    the per-launch HBM bytes of the FP32 stage kernels, each counter scaled by
+    what it reads for the plain device copies of one state buffer, and store
+    them with the kernel-source hash in the traffic file."""
+    import collections
+    import csv
+
+    def per_kernel(d):
+        acc = collections.defaultdict(list)
+        with open(os.path.join(d, "run_counter_collection.csv")) as fh:
+            for r in csv.DictReader(fh):
+                acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return acc
+
+    def find(acc, key):
+        ks = [k for k in acc if key in k]
+        if len(ks) != 1:
+            raise SystemExit("expected one kernel matching %r, found %s" % (key, ks))
+        return acc[ks[0]]
+
+    wl = workload_by_name(workload)
+    dof = wl.dof()
+    F, W = per_kernel(fetch_dir), per_kernel(write_dir)
+    n = wl.n
+    s1f, s23f = find(F, "stage2v_kernel<float, %d, false, false>" % n), find(F, "stage2v_kernel<float, %d, true, false>" % n)
+    s1w, s23w = find(W, "stage2v_kernel<float, %d, false, false>" % n), find(W, "stage2v_kernel<float, %d, true, false>" % n)
+    # the calibration copies: the large copyBuffer dispatches
+    cf = [v for v in find(F, "copyBuffer") if v > 1e5]
+    cw = [v for v in find(W, "copyBuffer") if v > 1e5]
+    from paper_2202_13532_amd import dg
+    cfg = dg.make_config(wl.nv, wl.n, wl.nelem, wl.lo, wl.hi, wl.omega_c, 0, "f32", layout="vpad")
+    state_bytes = math.prod(dg.state_shape(cfg)) * 4
+    mean = lambda x: sum(x) / len(x)
+    ff = mean(cf) * 1024 / state_bytes
+    fw = mean(cw) * 1024 / state_bytes
+    b1 = mean(s1f) * 1024 / ff + mean(s1w) * 1024 / fw
+    b23 = mean(s23f) * 1024 / ff + mean(s23w) * 1024 / fw
+    alg = [8 * dof, 12 * dof, 12 * dof]
+    rec = {workload + "_f32_vpad": {
+        "layout": "vpad", "kernel_sha256_16": kernel_source_hash(),
+        "bytes_per_launch": [b1, b23, b23], "algorithmic_bytes_per_launch": alg,
+        "fetch_kib_per_launch": [mean(s1f), mean(s23f)], "write_kib_per_launch": [mean(s1w), mean(s23w)],
+        "copy_calibration": {"bytes_each_way": state_bytes, "fetch_kib": mean(cf), "write_kib": mean(cw),
+                             "fetch_factor": ff, "write_factor": fw},
+        "launches_counted": {"stage1": len(s1f), "stage23": len(s23f)}}}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps({"traffic_over_algorithmic": [b1 / alg[0], b23 / alg[1]], "fetch_factor": ff,
+                      "write_factor": fw, "copies": [len(cf), len(cw)]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,7 +329,12 @@ def main():
     ap.add_argument("--pattern-copy", action="store_true",
                     help="print the bandwidth of a streaming copy and of a copy with the stage kernel's tile "
                          "access pattern (no halos, no arithmetic) next to the stage kernels'")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="summarise two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) into the traffic file; "
+                         "runs nothing on the GPU")
     args = ap.parse_args()
+    if args.write_traffic:
+        return write_traffic(*args.write_traffic, workload=args.workload)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the x-slab sharding is a design note); run with --gpus 1", file=sys.stderr)

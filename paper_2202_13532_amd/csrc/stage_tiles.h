@@ -651,29 +651,36 @@ __device__ __forceinline__ void stage1v_tile(const StageArgs<T> a, int bid, T* l
 // -------------------------------------------------------------------------
 // Field solve (FP64), two launches per stage (a kernel boundary orders the
 // hand-over; a device-scope fence would write back and invalidate L2).
-//   fieldA: block ix (one wave) reduces the density partials of its x element
-//           in a fixed order and forms its Fourier sums
+//   fieldA: block ix (256 threads) reduces the density partials of its x
+//           element in a fixed order and forms its Fourier sums
 //           sum_j T_p^{mj} (n_mj - 1)  (eq. spectral_transform) and its mass.
 //   fieldB: one block sums those in element order, synthesises E at every x
 //           node, E_mj = sum_{p=1..pmax} 2 Re((i / k_p) c_p e^{i k_p x_mj})
-//           (eq. electric_sol), with e^{i k_p x} from the recurrence
-//           z_p = z_{p-1} z_1, and writes the diagnostics record.
+//           (eq. electric_sol), as a polynomial in z = e^{i k_1 x_mj}
+//           evaluated by Horner's scheme, and writes the diagnostics record.
+// Each kernel issues every read that does not depend on its reduction in the
+// first memory round trip.
 // No float atomics: results are bitwise reproducible.
 // -------------------------------------------------------------------------
 constexpr int kFieldB = 1024;
 
 constexpr int kFieldA = 256;
 
+// Partials per thread and pass of fieldA: one pass covers 16 * 256 values,
+// all loads of a pass in flight together.
+constexpr int kLoadsA = 16;
+
 __device__ __forceinline__ void fieldA_body(const FieldArgs& a, int ix) {
   // every fused multiply-add is written out (fmadd): the rounding then does
   // not depend on the kernel this code is inlined into
   #pragma clang fp contract(off)
   __shared__ double dens[kMaxN];
+  __shared__ double wxs[kMaxN];
   __shared__ double red[kFieldA / kWave][kMaxN];
   const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave, n = a.n;
-  // the connection-tensor entries of this thread's first mode do not depend
-  // on the density: fetch them together with the partials (one memory round
-  // trip instead of two)
+  // Reads that do not depend on the density go out with the partials, in
+  // one memory round trip: the connection-tensor entries of this thread's
+  // first mode and the quadrature weights of the element (for its mass).
   double tr[kMaxN], ti[kMaxN];
   if (tid < a.pmax) {
 #pragma unroll
@@ -684,16 +691,35 @@ __device__ __forceinline__ void fieldA_body(const FieldArgs& a, int ix) {
         ti[j] = t[1];
       }
   }
-  // thread-strided partial sums for all x nodes at once (n loads in flight),
-  // wave sums, then the waves' results added in order
+  const double wxj = tid < n ? a.wx[ix * n + tid] : 0.0;
+  // The element's partials are n rows of ntiles values, contiguous: thread
+  // tid takes values tid, tid + 256, ... in passes of kLoadsA loads, each
+  // added to the sum of its row; then wave sums, and the waves' results
+  // added in order.
   double s[kMaxN];
 #pragma unroll
   for (int j = 0; j < kMaxN; ++j) s[j] = 0.0;
   const double* base = a.partials + static_cast<size_t>(ix * n) * a.ntiles;
-  for (int t = tid; t < a.ntiles; t += kFieldA) {
+  const int total = n * a.ntiles;
+  const float rnt = 1.0f / static_cast<float>(a.ntiles);
+  for (int q0 = 0; q0 < total; q0 += kFieldA * kLoadsA) {
+    double v[kLoadsA];
 #pragma unroll
-    for (int j = 0; j < kMaxN; ++j)
-      if (j < n) s[j] += base[static_cast<size_t>(j) * a.ntiles + t];
+    for (int q = 0; q < kLoadsA; ++q) {
+      const int idx = q0 + q * kFieldA + tid;
+      v[q] = idx < total ? base[idx] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kLoadsA; ++q) {
+      const int idx = q0 + q * kFieldA + tid;
+      // row of value idx (idx < 2^24: the float quotient is off by at most one)
+      int j = static_cast<int>(static_cast<float>(idx) * rnt);
+      j -= j * a.ntiles > idx ? 1 : 0;
+      j += (j + 1) * a.ntiles <= idx ? 1 : 0;
+#pragma unroll
+      for (int jj = 0; jj < kMaxN; ++jj)
+        if (jj == j) s[jj] += v[q];
+    }
   }
 #pragma unroll
   for (int j = 0; j < kMaxN; ++j) {
@@ -702,6 +728,7 @@ __device__ __forceinline__ void fieldA_body(const FieldArgs& a, int ix) {
       if (lane == 0) red[wid][j] = d;
     }
   }
+  if (tid < n) wxs[tid] = wxj;
   __syncthreads();
   if (tid < n) {
     double d = 0.0;
@@ -733,7 +760,7 @@ __device__ __forceinline__ void fieldA_body(const FieldArgs& a, int ix) {
   }
   if (tid == 0) {
     double m = 0.0;
-    for (int j = 0; j < n; ++j) m = __builtin_fma(a.wx[ix * n + j], dens[j], m);
+    for (int j = 0; j < n; ++j) m = __builtin_fma(wxs[j], dens[j], m);
     a.mpart[ix] = m;
   }
 }
@@ -747,14 +774,18 @@ __device__ __forceinline__ void fieldB_body(const FieldArgs& a) {
   __shared__ double wred[2][kFieldB / kWave];
   __shared__ double mass_sh;
   const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
-  // mass: wave 0 adds the element partials (lane-strided, then a fixed
-  // exchange pattern) while the others start on the coefficients
-  if (wid == 0) {
-    double mp = 0.0;
-    for (int e = lane; e < a.Nx; e += kWave) mp += a.mpart[e];
-    mp = wave_sum(mp);
-    if (lane == 0) mass_sh = mp;
+  const int nodes = a.Nx * a.n;
+  // Reads that do not depend on the coefficients go out first, in the same
+  // round trip as the element partials: this thread's first x node (z_1 and
+  // its weight), the first 64 mass partials and the record counter.
+  double z1r0 = 0.0, z1i0 = 0.0, wx0 = 0.0;
+  if (tid < nodes) {
+    z1r0 = a.z1[2 * tid];
+    z1i0 = a.z1[2 * tid + 1];
+    wx0 = a.wx[tid];
   }
+  const double mp0 = (wid == 0 && lane < a.Nx) ? a.mpart[lane] : 0.0;
+  const int k = (tid == 0 && a.record && a.ring) ? *a.counter : -1;
   // c_p = sum over elements of the element partials, 64 modes at a time:
   // G = 16 groups of threads, each adding a contiguous G-th of the elements
   // for one mode (its loads in flight together), the groups' sums then added
@@ -792,20 +823,33 @@ __device__ __forceinline__ void fieldB_body(const FieldArgs& a) {
     }
     __syncthreads();
   }
-  // E at every x node: the modes by the recurrence z_p = z_{p-1} z_1
-  const int nodes = a.Nx * a.n;
+  // mass: wave 0 adds the element partials (lane-strided, then a fixed
+  // exchange pattern)
+  if (wid == 0) {
+    double mp = mp0;
+    for (int e = lane + kWave; e < a.Nx; e += kWave) mp += a.mpart[e];
+    mp = wave_sum(mp);
+    if (lane == 0) mass_sh = mp;
+  }
+  // E at every x node: E = Im(sum_p a_p z^p) with z = e^{i k_1 x} and a_p
+  // the scaled coefficients, by Horner's scheme, S = z (a_1 + z (a_2 + ...
+  // + z a_pmax)): four fused multiply-adds per mode
   double fe = 0.0, mx = 0.0;
   for (int node = tid; node < nodes; node += kFieldB) {
-    const double z1r = a.z1[2 * node], z1i = a.z1[2 * node + 1];
-    double zr = z1r, zi = z1i, e = 0.0;
-    for (int p = 0; p < a.pmax; ++p) {
-      e += __builtin_fma(csh[2 * p], zi, csh[2 * p + 1] * zr);
-      const double t = __builtin_fma(zr, z1r, -(zi * z1i));
-      zi = __builtin_fma(zr, z1i, zi * z1r);
-      zr = t;
+    const bool first = node == tid;
+    const double z1r = first ? z1r0 : a.z1[2 * node];
+    const double z1i = first ? z1i0 : a.z1[2 * node + 1];
+    const double w = first ? wx0 : a.wx[node];
+    double ar = 0.0, ai = 0.0;
+    for (int p = a.pmax - 1; p >= 0; --p) {
+      const double nr = __builtin_fma(z1r, ar, __builtin_fma(-z1i, ai, csh[2 * p]));
+      const double ni = __builtin_fma(z1r, ai, __builtin_fma(z1i, ar, csh[2 * p + 1]));
+      ar = nr;
+      ai = ni;
     }
+    const double e = __builtin_fma(z1r, ai, z1i * ar);
     a.E[node] = e;
-    fe = __builtin_fma(a.wx[node] * e, e, fe);
+    fe = __builtin_fma(w * e, e, fe);
     mx = fmax(mx, fabs(e));
   }
   // field energy and max |E|: per wave, then the waves in order
@@ -825,7 +869,6 @@ __device__ __forceinline__ void fieldB_body(const FieldArgs& a) {
     const double m = mass_sh + a.mass0;
     const double fen = 0.5 * fsum;
     const bool fin = isfinite(m) && isfinite(fen) && isfinite(fmx);
-    const int k = (a.record && a.ring) ? *a.counter : -1;
     double rec[8] = {0.0, m, fen, 0.0, 0.0, fmx, fin ? 1.0 : 0.0, static_cast<double>(k)};
     for (int q = 0; q < 8; ++q) a.last[q] = rec[q];
     if (k >= 0) {

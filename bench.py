@@ -38,9 +38,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# the single-run stage kernels: their launch code and the shared tile code
+# the stage kernels' source: the tile code with the kernel templates, and the
+# operator tables they are built with
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_13532_amd", "csrc", f)
-                  for f in ("dg_kernels.hip", "stage_tiles.h", "dg_ops_constexpr.h")]
+                  for f in ("stage_tiles.h", "dg_ops_constexpr.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_traffic.json")
 
 
@@ -323,7 +324,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched 64-run sweep sub-record")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage sub-record")
     ap.add_argument("--fp64-steps", type=int, default=20)
-    ap.add_argument("--sweep-steps", type=int, default=10)
+    ap.add_argument("--sweep-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run two plain device copies of one state buffer (reference for HBM byte counters)")
     ap.add_argument("--pattern-copy", action="store_true",

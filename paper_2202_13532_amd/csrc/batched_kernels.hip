@@ -2,6 +2,7 @@
 // independent runs stepped together, FP32 storage), with their launchers.
 #include <hip/hip_runtime.h>
 
+#include "field_bodies.h"
 #include "stage_tiles.h"
 
 namespace dgk {
@@ -90,7 +91,7 @@ __global__ void __launch_bounds__(kWave) stage_batched_1v_kernel(const StageArgs
 // block r of fieldB serves run r.
 __global__ void __launch_bounds__(kFieldA) fieldA_batched_kernel(const FieldArgs* __restrict__ fa, const int2* __restrict__ items) {
   const int2 it = items[blockIdx.x];
-  fieldA_body(fa[it.x], it.y);
+  fieldA_body<8, false>(fa[it.x], it.y);
 }
 __global__ void __launch_bounds__(kFieldB) fieldB_batched_kernel(const FieldArgs* __restrict__ fa) {
   fieldB_body(fa[blockIdx.x]);

@@ -997,6 +997,8 @@ struct dg_batch {
   int2* d_items = nullptr;
   int* d_xcd = nullptr;                       // 9 per kind
   dgk::FieldArgs* d_fa = nullptr;             // 3 * nruns (record flag differs)
+  dgk::FieldArgs* d_fa0 = nullptr;            // nruns: the field of the current states (no record)
+  double* d_last = nullptr;                   // 8 * nruns: their records, contiguous
   int2* d_xitems = nullptr;
   int nitems = 0, nxitems = 0, max_pmax = 0;
   // runs of one kind (n, nv): items [begin, begin + count) of the work list
@@ -1022,7 +1024,7 @@ constexpr size_t kBatchTail = 1 << 16;
 
 struct BatchLayout {
   std::vector<size_t> run_off;
-  size_t args, items, xcd, fa, xitems, total;
+  size_t args, items, xcd, fa, fa0, last, xitems, total;
 };
 
 BatchLayout batch_layout(const dg_config* cfgs, int nruns) {
@@ -1041,6 +1043,8 @@ BatchLayout batch_layout(const dg_config* cfgs, int nruns) {
   B.items = take(static_cast<size_t>(ntiles) * sizeof(int2));
   B.xcd = take(9 * static_cast<size_t>(nruns) * sizeof(int));
   B.fa = take(3 * nruns * sizeof(dgk::FieldArgs));
+  B.fa0 = take(nruns * sizeof(dgk::FieldArgs));
+  B.last = take(8 * static_cast<size_t>(nruns) * sizeof(double));
   B.xitems = take(static_cast<size_t>(nx) * sizeof(int2));
   B.total = o;
   return B;
@@ -1183,16 +1187,19 @@ dg_status batch_begin(dg_batch* b, void* const* f, const double* dt) {
   DGB_HIP(b, hipEventRecord(b->ev_in, b->user));
   DGB_HIP(b, hipStreamWaitEvent(b->stream, b->ev_in, 0));
   for (int r = 0; r < b->nruns; ++r) {
-    dg_ctx* c = b->runs[r];
     if (!f[r]) return bfail(b, DG_ERR_INVALID, "f[r] is NULL");
     if (!(dt[r] > 0.0) || !std::isfinite(dt[r])) return bfail(b, DG_ERR_INVALID, "dt[r] must be positive and finite");
+  }
+  // the field of the current states: density partials per run, then one
+  // batched field launch pair and one read-back of all records
+  for (int r = 0; r < b->nruns; ++r) {
+    dg_ctx* c = b->runs[r];
     dg_status s = density(c, f[r]);
-    if (s == DG_OK) s = field(c, c->at<double>(c->L.off_E), nullptr, false);
     if (s != DG_OK) return bfail(b, s, c->err);
   }
+  DGB_HIP(b, dgk::launch_field_batched(b->d_fa0, b->d_xitems, b->nxitems, b->nruns, b->max_pmax, b->stream));
   std::vector<double> last(8 * b->nruns);
-  for (int r = 0; r < b->nruns; ++r)
-    DGB_HIP(b, hipMemcpyAsync(&last[8 * r], b->runs[r]->at<double>(b->runs[r]->L.off_last), 64, hipMemcpyDeviceToHost, b->stream));
+  DGB_HIP(b, hipMemcpyAsync(last.data(), b->d_last, last.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream));
   DGB_HIP(b, hipStreamSynchronize(b->stream));
   for (int r = 0; r < b->nruns; ++r) {
     if (!std::isfinite(last[8 * r + 5]) || last[8 * r + 6] == 0.0) {
@@ -1278,6 +1285,8 @@ dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, s
   b->d_xcd = reinterpret_cast<int*>(b->ws + BL.xcd);
   b->d_fa = reinterpret_cast<dgk::FieldArgs*>(b->ws + BL.fa);
   b->d_xitems = reinterpret_cast<int2*>(b->ws + BL.xitems);
+  b->d_fa0 = reinterpret_cast<dgk::FieldArgs*>(b->ws + BL.fa0);
+  b->d_last = reinterpret_cast<double*>(b->ws + BL.last);
   int dev = 0;
   hipDeviceProp_t prop;
   if ((e = hipGetDevice(&dev)) != hipSuccess || (e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
@@ -1335,6 +1344,16 @@ dg_status dg_batch_init(const dg_config* cfgs, int32_t nruns, void* workspace, s
   b->nitems = static_cast<int>(b->items_cost.size());
   b->nxitems = static_cast<int>(xitems.size());
   if ((e = hipMemcpyAsync(b->d_xitems, xitems.data(), xitems.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream)) != hipSuccess)
+    return cleanup(DG_ERR_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
+  // field of the current states (each call's first step needs it): one
+  // batched launch pair, every run's record into one contiguous array
+  std::vector<dgk::FieldArgs> fa0(nruns);
+  for (int r = 0; r < nruns; ++r) {
+    dg_ctx* c = b->runs[r];
+    fill_field(c, &fa0[r], c->at<double>(c->L.off_E), nullptr, false);
+    fa0[r].last = b->d_last + 8 * r;
+  }
+  if ((e = hipMemcpyAsync(b->d_fa0, fa0.data(), fa0.size() * sizeof(fa0[0]), hipMemcpyHostToDevice, b->stream)) != hipSuccess)
     return cleanup(DG_ERR_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
   if (upload_items(b) != DG_OK) return cleanup(DG_ERR_DEVICE, b->err);
   *out = b;

@@ -17,28 +17,12 @@
 //   so the flux contraction is the speed times the contraction of f.
 #include <hip/hip_runtime.h>
 
+#include "field_bodies.h"
 #include "stage_tiles.h"
 
 namespace dgk {
 
-template <typename T, int N>
-constexpr int stage_min_waves() { return sizeof(T) == 8 && N >= 9 && N <= 11 ? 1 : 2; }
 
-template <typename T, int N, bool UN, bool BG>
-__global__ void __launch_bounds__(kWave, (stage_min_waves<T, N>())) stage2v_kernel(StageArgs<T> a) {
-  __shared__ T lds[lds_words_2v<N>()];
-  __shared__ T hbuf[N * N];
-  __shared__ double dsum[dens_words<T, N>()];
-  // reversed order: the tiles the previous stage wrote last are read first
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  stage2v_tile<T, N, UN, BG>(a, a.reverse ? static_cast<int>(gridDim.x) - 1 - b : b, lds, hbuf, dsum);
-}
-
-template <typename T, int N, bool UN, bool BG>
-__global__ void __launch_bounds__(kWave) stage1v_kernel(StageArgs<T> a) {
-  __shared__ T lds[lds_words_1v<N>()];
-  stage1v_tile<T, N, UN, BG>(a, xcd_remap(blockIdx.x, gridDim.x), lds);
-}
 
 // -------------------------------------------------------------------------
 // Density partials only (same tiles and partial layout as the stage kernels).
@@ -154,7 +138,7 @@ __global__ void __launch_bounds__(kWave) moments_kernel(StageArgs<T> a, double* 
   }
 }
 
-__global__ void __launch_bounds__(kFieldA) fieldA_kernel(FieldArgs a) { fieldA_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(kFieldA) fieldA_kernel(FieldArgs a) { fieldA_body<16, true>(a, blockIdx.x); }
 __global__ void __launch_bounds__(kFieldB) fieldB_kernel(FieldArgs a) { fieldB_body(a); }
 
 constexpr int kFieldThreads = 256;

@@ -1,7 +1,7 @@
-// Device code shared by the single-run and the batched kernels: wave
-// reductions, buffer access, the 1D2V and 1D1V stage tiles and the bodies of
-// the FP64 field solve.  Included by dg_kernels.hip and batched_kernels.hip
-// (each kernel instantiates what it needs).
+// Stage code shared by the single-run and the batched kernels: wave
+// reductions, buffer access, the 1D2V and 1D1V stage tiles and the
+// single-run stage kernel templates.  Included by dg_kernels.hip and
+// batched_kernels.hip (each instantiates what it launches).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -530,14 +530,6 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
   }
 }
 
-// FP64 slabs of n = 9 do not fit 256 VGPRs; at one wave per SIMD the
-// compiler may also use the accumulation registers instead of spilling to
-// scratch memory.  FP64 n = 12 (476 registers at one wave per SIMD) is built
-// for two waves per SIMD with scratch spills: the one-wave build of this
-// same source returned wrong values for one v pencil (x node 6, u node 4,
-// first element of each chunk) whenever the v term was active, while the
-// two-wave build matches the oracle to 1.7e-15.
-
 // -------------------------------------------------------------------------
 // 1D1V stage kernel.  state [Nx, N, Nv, N]; x speed v, v speed -E(x).
 // -------------------------------------------------------------------------
@@ -647,237 +639,33 @@ __device__ __forceinline__ void stage1v_tile(const StageArgs<T> a, int bid, T* l
   }
 }
 
-
 // -------------------------------------------------------------------------
-// Field solve (FP64), two launches per stage (a kernel boundary orders the
-// hand-over; a device-scope fence would write back and invalidate L2).
-//   fieldA: block ix (256 threads) reduces the density partials of its x
-//           element in a fixed order and forms its Fourier sums
-//           sum_j T_p^{mj} (n_mj - 1)  (eq. spectral_transform) and its mass.
-//   fieldB: one block sums those in element order, synthesises E at every x
-//           node, E_mj = sum_{p=1..pmax} 2 Re((i / k_p) c_p e^{i k_p x_mj})
-//           (eq. electric_sol), as a polynomial in z = e^{i k_1 x_mj}
-//           evaluated by Horner's scheme, and writes the diagnostics record.
-// Each kernel issues every read that does not depend on its reduction in the
-// first memory round trip.
-// No float atomics: results are bitwise reproducible.
+// Single-run stage kernels: one tile per work-group.
 // -------------------------------------------------------------------------
-constexpr int kFieldB = 1024;
+// FP64 slabs of n = 9 do not fit 256 VGPRs; at one wave per SIMD the
+// compiler may also use the accumulation registers instead of spilling to
+// scratch memory.  FP64 n = 12 (476 registers at one wave per SIMD) is built
+// for two waves per SIMD with scratch spills: the one-wave build of this
+// same source returned wrong values for one v pencil (x node 6, u node 4,
+// first element of each chunk) whenever the v term was active, while the
+// two-wave build matches the oracle to 1.7e-15.
+template <typename T, int N>
+constexpr int stage_min_waves() { return sizeof(T) == 8 && N >= 9 && N <= 11 ? 1 : 2; }
 
-constexpr int kFieldA = 256;
-
-// Partials per thread and pass of fieldA: one pass covers 16 * 256 values,
-// all loads of a pass in flight together.
-constexpr int kLoadsA = 16;
-
-__device__ __forceinline__ void fieldA_body(const FieldArgs& a, int ix) {
-  // every fused multiply-add is written out (fmadd): the rounding then does
-  // not depend on the kernel this code is inlined into
-  #pragma clang fp contract(off)
-  __shared__ double dens[kMaxN];
-  __shared__ double wxs[kMaxN];
-  __shared__ double red[kFieldA / kWave][kMaxN];
-  const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave, n = a.n;
-  // Reads that do not depend on the density go out with the partials, in
-  // one memory round trip: the connection-tensor entries of this thread's
-  // first mode and the quadrature weights of the element (for its mass).
-  double tr[kMaxN], ti[kMaxN];
-  if (tid < a.pmax) {
-#pragma unroll
-    for (int j = 0; j < kMaxN; ++j)
-      if (j < n) {
-        const double* t = a.T + 2 * (static_cast<size_t>(ix * n + j) * a.pmax + tid);
-        tr[j] = t[0];
-        ti[j] = t[1];
-      }
-  }
-  const double wxj = tid < n ? a.wx[ix * n + tid] : 0.0;
-  // The element's partials are n rows of ntiles values, contiguous: thread
-  // tid takes values tid, tid + 256, ... in passes of kLoadsA loads, each
-  // added to the sum of its row; then wave sums, and the waves' results
-  // added in order.
-  double s[kMaxN];
-#pragma unroll
-  for (int j = 0; j < kMaxN; ++j) s[j] = 0.0;
-  const double* base = a.partials + static_cast<size_t>(ix * n) * a.ntiles;
-  const int total = n * a.ntiles;
-  const float rnt = 1.0f / static_cast<float>(a.ntiles);
-  for (int q0 = 0; q0 < total; q0 += kFieldA * kLoadsA) {
-    double v[kLoadsA];
-#pragma unroll
-    for (int q = 0; q < kLoadsA; ++q) {
-      const int idx = q0 + q * kFieldA + tid;
-      v[q] = idx < total ? base[idx] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < kLoadsA; ++q) {
-      const int idx = q0 + q * kFieldA + tid;
-      // row of value idx (idx < 2^24: the float quotient is off by at most one)
-      int j = static_cast<int>(static_cast<float>(idx) * rnt);
-      j -= j * a.ntiles > idx ? 1 : 0;
-      j += (j + 1) * a.ntiles <= idx ? 1 : 0;
-#pragma unroll
-      for (int jj = 0; jj < kMaxN; ++jj)
-        if (jj == j) s[jj] += v[q];
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < kMaxN; ++j) {
-    if (j < n) {
-      const double d = wave_sum(s[j]);
-      if (lane == 0) red[wid][j] = d;
-    }
-  }
-  if (tid < n) wxs[tid] = wxj;
-  __syncthreads();
-  if (tid < n) {
-    double d = 0.0;
-    for (int w = 0; w < kFieldA / kWave; ++w) d += red[w][tid];
-    dens[tid] = d;
-    a.dens[ix * n + tid] = d;
-  }
-  __syncthreads();
-  for (int p = tid; p < a.pmax; p += kFieldA) {
-    double cr = 0.0, ci = 0.0;
-    if (p == tid) {
-#pragma unroll
-      for (int j = 0; j < kMaxN; ++j)
-        if (j < n) {
-          const double sj = dens[j] - 1.0;
-          cr = __builtin_fma(tr[j], sj, cr);
-          ci = __builtin_fma(ti[j], sj, ci);
-        }
-    } else {
-      for (int j = 0; j < n; ++j) {
-        const double* t = a.T + 2 * (static_cast<size_t>(ix * n + j) * a.pmax + p);
-        const double sj = dens[j] - 1.0;
-        cr = __builtin_fma(t[0], sj, cr);
-        ci = __builtin_fma(t[1], sj, ci);
-      }
-    }
-    a.cpart[2 * (static_cast<size_t>(ix) * a.pmax + p) + 0] = cr;
-    a.cpart[2 * (static_cast<size_t>(ix) * a.pmax + p) + 1] = ci;
-  }
-  if (tid == 0) {
-    double m = 0.0;
-    for (int j = 0; j < n; ++j) m = __builtin_fma(wxs[j], dens[j], m);
-    a.mpart[ix] = m;
-  }
+template <typename T, int N, bool UN, bool BG>
+__global__ void __launch_bounds__(kWave, (stage_min_waves<T, N>())) stage2v_kernel(StageArgs<T> a) {
+  __shared__ T lds[lds_words_2v<N>()];
+  __shared__ T hbuf[N * N];
+  __shared__ double dsum[dens_words<T, N>()];
+  // reversed order: the tiles the previous stage wrote last are read first
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  stage2v_tile<T, N, UN, BG>(a, a.reverse ? static_cast<int>(gridDim.x) - 1 - b : b, lds, hbuf, dsum);
 }
 
-__device__ __forceinline__ void fieldB_body(const FieldArgs& a) {
-  // every fused multiply-add is written out (fmadd): the rounding then does
-  // not depend on the kernel this code is inlined into
-  #pragma clang fp contract(off)
-  extern __shared__ double csh[];          // 2 * pmax scaled coefficients
-  __shared__ double red[2][kFieldB];
-  __shared__ double wred[2][kFieldB / kWave];
-  __shared__ double mass_sh;
-  const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
-  const int nodes = a.Nx * a.n;
-  // Reads that do not depend on the coefficients go out first, in the same
-  // round trip as the element partials: this thread's first x node (z_1 and
-  // its weight), the first 64 mass partials and the record counter.
-  double z1r0 = 0.0, z1i0 = 0.0, wx0 = 0.0;
-  if (tid < nodes) {
-    z1r0 = a.z1[2 * tid];
-    z1i0 = a.z1[2 * tid + 1];
-    wx0 = a.wx[tid];
-  }
-  const double mp0 = (wid == 0 && lane < a.Nx) ? a.mpart[lane] : 0.0;
-  const int k = (tid == 0 && a.record && a.ring) ? *a.counter : -1;
-  // c_p = sum over elements of the element partials, 64 modes at a time:
-  // G = 16 groups of threads, each adding a contiguous G-th of the elements
-  // for one mode (its loads in flight together), the groups' sums then added
-  // in order.
-  constexpr int PB = kWave, G = kFieldB / PB;
-  for (int base = 0; base < a.pmax; base += PB) {
-    const int p = base + tid % PB;
-    const int g = tid / PB;
-    double cr = 0.0, ci = 0.0;
-    if (p < a.pmax) {
-      const int e0 = g * a.Nx / G, e1 = (g + 1) * a.Nx / G;
-#pragma unroll 8
-      for (int e = e0; e < e1; ++e) {
-        cr += a.cpart[2 * (static_cast<size_t>(e) * a.pmax + p) + 0];
-        ci += a.cpart[2 * (static_cast<size_t>(e) * a.pmax + p) + 1];
-      }
-    }
-    red[0][tid] = cr;
-    red[1][tid] = ci;
-    __syncthreads();
-    if (tid < PB && base + tid < a.pmax) {
-      double r = 0.0, i = 0.0;
-      for (int q = 0; q < G; ++q) {
-        r += red[0][q * PB + tid];
-        i += red[1][q * PB + tid];
-      }
-      if (a.coeffs) {
-        a.coeffs[2 * (base + tid)] = r;
-        a.coeffs[2 * (base + tid) + 1] = i;
-      }
-      // 2 Re((i / k_p) c_p z) = -(2 / k_p) Im(c_p z): fold -2 / k_p in once
-      const double sc = -2.0 / ((base + tid + 1) * a.k1);
-      csh[2 * (base + tid)] = sc * r;
-      csh[2 * (base + tid) + 1] = sc * i;
-    }
-    __syncthreads();
-  }
-  // mass: wave 0 adds the element partials (lane-strided, then a fixed
-  // exchange pattern)
-  if (wid == 0) {
-    double mp = mp0;
-    for (int e = lane + kWave; e < a.Nx; e += kWave) mp += a.mpart[e];
-    mp = wave_sum(mp);
-    if (lane == 0) mass_sh = mp;
-  }
-  // E at every x node: E = Im(sum_p a_p z^p) with z = e^{i k_1 x} and a_p
-  // the scaled coefficients, by Horner's scheme, S = z (a_1 + z (a_2 + ...
-  // + z a_pmax)): four fused multiply-adds per mode
-  double fe = 0.0, mx = 0.0;
-  for (int node = tid; node < nodes; node += kFieldB) {
-    const bool first = node == tid;
-    const double z1r = first ? z1r0 : a.z1[2 * node];
-    const double z1i = first ? z1i0 : a.z1[2 * node + 1];
-    const double w = first ? wx0 : a.wx[node];
-    double ar = 0.0, ai = 0.0;
-    for (int p = a.pmax - 1; p >= 0; --p) {
-      const double nr = __builtin_fma(z1r, ar, __builtin_fma(-z1i, ai, csh[2 * p]));
-      const double ni = __builtin_fma(z1r, ai, __builtin_fma(z1i, ar, csh[2 * p + 1]));
-      ar = nr;
-      ai = ni;
-    }
-    const double e = __builtin_fma(z1r, ai, z1i * ar);
-    a.E[node] = e;
-    fe = __builtin_fma(w * e, e, fe);
-    mx = fmax(mx, fabs(e));
-  }
-  // field energy and max |E|: per wave, then the waves in order
-  fe = wave_sum(fe);
-  mx = wave_max(mx);
-  if (lane == 0) {
-    wred[0][wid] = fe;
-    wred[1][wid] = mx;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double fsum = 0.0, fmx = 0.0;
-    for (int w = 0; w < kFieldB / kWave; ++w) {
-      fsum += wred[0][w];
-      fmx = fmax(fmx, wred[1][w]);
-    }
-    const double m = mass_sh + a.mass0;
-    const double fen = 0.5 * fsum;
-    const bool fin = isfinite(m) && isfinite(fen) && isfinite(fmx);
-    double rec[8] = {0.0, m, fen, 0.0, 0.0, fmx, fin ? 1.0 : 0.0, static_cast<double>(k)};
-    for (int q = 0; q < 8; ++q) a.last[q] = rec[q];
-    if (k >= 0) {
-      double* r = a.ring + 8 * (k % kRing);
-      for (int q = 0; q < 8; ++q) r[q] = rec[q];
-      *a.counter = k + 1;
-    }
-  }
+template <typename T, int N, bool UN, bool BG>
+__global__ void __launch_bounds__(kWave) stage1v_kernel(StageArgs<T> a) {
+  __shared__ T lds[lds_words_1v<N>()];
+  stage1v_tile<T, N, UN, BG>(a, xcd_remap(blockIdx.x, gridDim.x), lds);
 }
-
 
 }  // namespace dgk

@@ -276,8 +276,9 @@ dg_status dg_batch_rk_step(dg_batch* b, void* const* f, const double* dt, int32_
 
 /* Autotuner: time `reps` batched steps per candidate and keep the fastest
  * for this batch: first the work-list order (cost-sorted or run-interleaved),
- * then, per kind (n, nv), its persistent grid (work-groups per CU from 1 to
- * the kind's occupancy limit), one kind at a time, largest first.  The
+ * then, per kind (n, nv), its launch shape (a persistent grid of 1 to the
+ * kind's occupancy limit work-groups per CU, or one work-group per tile),
+ * one kind at a time, largest first.  The
  * per-kind grids are kept per (GPU arch, n, nv, FP32) for the life of the
  * process and start later batches.  Returns the
  * mean step time in ms of the choice; the states are advanced by the timed
@@ -290,7 +291,7 @@ int32_t dg_batch_grid(const dg_batch* b);
 /* The current choices: returns the number of kinds K; if host_out != NULL it
  * receives 2 + 4 K ints: [concurrent kind launches (always 0: the form is
  * switched off), order (0 cost-sorted, 1 run-interleaved), then per kind n,
- * nv, work-groups per CU, grid].                                            */
+ * nv, work-groups per CU (0: one work-group per tile), grid].              */
 int32_t dg_batch_choice(const dg_batch* b, int32_t* host_out);
 /* Apply choices in the layout dg_batch_choice returns (nint = 2 + 4 K; the
  * kinds must be this batch's, in its order; the grid entries are ignored and

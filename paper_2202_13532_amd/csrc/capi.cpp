@@ -342,8 +342,7 @@ dg_status enqueue_step(dg_ctx* c, void* f, double dt, bool diag, bool odd) {
 dg_status build_graph(dg_ctx* c, void* f, double dt, bool diag) {
   if (c->gexec && c->g_f == f && c->g_dt == dt && c->g_diag == diag) return DG_OK;
   if (c->gexec) {
-    (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
+    drop_graph(c->stream, &c->gexec);
   }
   // the graph holds a pair of steps (the two tile-order patterns)
   DG_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -819,8 +818,7 @@ dg_status dg_set_background(dg_ctx* ctx, const double* f0) {
   if (!ctx) return DG_ERR_INVALID;
   // a cached step graph holds the stage kernels of the previous mode
   if (ctx->gexec) {
-    (void)hipGraphExecDestroy(ctx->gexec);
-    ctx->gexec = nullptr;
+    drop_graph(ctx->stream, &ctx->gexec);
   }
   if (!f0) {
     ctx->bg = false;
@@ -1093,8 +1091,10 @@ dg_status upload_items(dg_batch* b) {
     std::vector<int> x = xcd_split(part, cost);
     xcd.insert(xcd.end(), x.begin(), x.end());
     const int occ = std::max(1, std::min(g.occ[0], g.occ[1]));
-    // at least one work-group per XCD range (8), else a range would be skipped
-    g.grid = std::max(8, std::min(g.count, b->cus * std::min(g.wm, occ)));
+    // wm = 0: one work-group per tile (the hardware dispatcher balances the
+    // CUs); else a persistent grid of wm work-groups per CU.  At least one
+    // work-group per XCD range (8), else a range would be skipped.
+    g.grid = g.wm == 0 ? std::max(8, g.count) : std::max(8, std::min(g.count, b->cus * std::min(g.wm, occ)));
   }
   DGB_HIP(b, hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
   DGB_HIP(b, hipMemcpyAsync(b->d_xcd, xcd.data(), xcd.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
@@ -1155,10 +1155,7 @@ dg_status build_batch_graph(dg_batch* b, void* const* f, const double* dt, bool 
   bool same = b->gexec && b->g_diag == diag;
   for (int r = 0; same && r < b->nruns; ++r) same = b->g_f[r] == f[r] && b->g_dt[r] == dt[r];
   if (same) return DG_OK;
-  if (b->gexec) {
-    (void)hipGraphExecDestroy(b->gexec);
-    b->gexec = nullptr;
-  }
+  drop_graph(b->stream, &b->gexec);
   b->g_f.assign(f, f + b->nruns);
   b->g_dt.assign(dt, dt + b->nruns);
   b->g_diag = diag;
@@ -1431,10 +1428,7 @@ dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t r
   auto measure = [&](double* ms_out) -> dg_status {
     dg_status st = upload_items(b);
     if (st != DG_OK) return st;
-    if (b->gexec) {
-      (void)hipGraphExecDestroy(b->gexec);
-      b->gexec = nullptr;
-    }
+    drop_graph(b->stream, &b->gexec);
     st = build_batch_graph(b, f, dt, false);
     if (st != DG_OK) return st;
     DGB_HIP(b, hipGraphLaunch(b->gexec, b->stream));
@@ -1463,8 +1457,10 @@ dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t r
     }
   }
   b->order = best_order;
-  // 2. per kind (n, nv): its work-groups per CU, one kind at a time with the
-  //    others at their current best (coordinate descent, largest kinds first)
+  // 2. per kind (n, nv): its launch shape, one kind at a time with the others
+  //    at their current best (coordinate descent, largest kinds first): a
+  //    persistent grid of 1 .. occupancy work-groups per CU, or one
+  //    work-group per tile (wm = 0)
   std::vector<size_t> byc(b->groups.size());
   for (size_t q = 0; q < byc.size(); ++q) byc[q] = q;
   std::stable_sort(byc.begin(), byc.end(), [&](size_t p, size_t q) { return b->groups[p].count > b->groups[q].count; });
@@ -1472,7 +1468,11 @@ dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t r
     if (s != DG_OK) break;
     auto& g = b->groups[q];
     int best_w = g.wm;
-    for (int w = 1; w < occ_of(g) && s == DG_OK; ++w) {
+    std::vector<int> cand;
+    for (int w = 1; w < occ_of(g); ++w) cand.push_back(w);
+    cand.push_back(0);
+    for (int w : cand) {
+      if (s != DG_OK) break;
       g.wm = w;
       double ms = 0.0;
       s = measure(&ms);
@@ -1489,10 +1489,7 @@ dg_status dg_batch_tune(dg_batch* b, void* const* f, const double* dt, int32_t r
   for (const auto& g : b->groups) tune_cache_put(b->arch, g.n, g.nv, g.wm);
   s = upload_items(b);
   if (s != DG_OK) return s;
-  if (b->gexec) {
-    (void)hipGraphExecDestroy(b->gexec);
-    b->gexec = nullptr;
-  }
+  drop_graph(b->stream, &b->gexec);
   if (best_ms) *best_ms = best;
   return batch_leave(b);
 }
@@ -1525,14 +1522,12 @@ dg_status dg_batch_set_choice(dg_batch* b, const int32_t* choice, int32_t nint) 
     const auto& g = b->groups[q];
     if (choice[2 + 4 * q] != g.n || choice[3 + 4 * q] != g.nv)
       return bfail(b, DG_ERR_INVALID, "dg_batch_set_choice: kinds differ from this batch's");
-    if (choice[4 + 4 * q] < 1) return bfail(b, DG_ERR_INVALID, "dg_batch_set_choice: work-groups per CU must be >= 1");
+    if (choice[4 + 4 * q] < 0)
+      return bfail(b, DG_ERR_INVALID, "dg_batch_set_choice: work-groups per CU must be >= 0 (0: one per tile)");
   }
   b->order = choice[1];
   for (int q = 0; q < nk; ++q) b->groups[q].wm = choice[4 + 4 * q];
-  if (b->gexec) {
-    (void)hipGraphExecDestroy(b->gexec);
-    b->gexec = nullptr;
-  }
+  drop_graph(b->stream, &b->gexec);
   return upload_items(b);
 }
 

@@ -79,4 +79,13 @@ const char* config_error(const dg_config* cfg, dg_status* st);
 // Record msg as the context-free error (dg_last_error(NULL)) and return s.
 dg_status global_fail(dg_status s, const std::string& msg);
 
+// Destroy an executable graph once the stream that replays it is idle (a
+// caller may have launched it and returned without waiting); *g = NULL.
+inline void drop_graph(hipStream_t stream, hipGraphExec_t* g) {
+  if (!*g) return;
+  (void)hipStreamSynchronize(stream);
+  (void)hipGraphExecDestroy(*g);
+  *g = nullptr;
+}
+
 }  // namespace dgi

@@ -752,6 +752,8 @@ dg_status build_corrected_graph(dg_ctx* c, dg_nn* nn, const float* mean, const f
       nn->g_scale == scale && nn->g_diag == diag)
     return DG_OK;
   if (nn->gexec) {
+    // the old graph may still replay, on this or another context's stream
+    (void)hipDeviceSynchronize();
     (void)hipGraphExecDestroy(nn->gexec);
     nn->gexec = nullptr;
   }

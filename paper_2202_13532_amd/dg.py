@@ -483,6 +483,8 @@ def dg_batch_grid(b):
 
 
 def dg_batch_choice(b):
+    """The batch's launch choices; per kind wg_per_cu is the persistent grid
+    in work-groups per CU, 0 for one work-group per tile."""
     k = int(lib().dg_batch_choice(b, None))
     out = (ctypes.c_int32 * (2 + 4 * k))()
     lib().dg_batch_choice(b, out)

@@ -182,7 +182,7 @@ def _launch_form_check(concurrent_forms):
     for conc in concurrent_forms:
         for order in ("cost-sorted", "run-interleaved"):
             ch = {"concurrent": conc, "order": order,
-                  "kinds": [dict(k, wg_per_cu=1 + (i % 2)) for i, k in enumerate(base["kinds"])]}
+                  "kinds": [dict(k, wg_per_cu=i % 3) for i, k in enumerate(base["kinds"])]}
             B.choice = ch
             got = B.choice
             assert got["concurrent"] == conc and got["order"] == order
@@ -194,8 +194,9 @@ def _launch_form_check(concurrent_forms):
 
 
 def test_batch_orders_grids_and_tuner_keep_bitwise_equality():
-    """Both work-list orders, any per-kind grid and the tuner's choice give
-    the solo runs' results bit for bit."""
+    """Both work-list orders, any per-kind launch shape (persistent grids of
+    1 or 2 work-groups per CU, one work-group per tile) and the tuner's choice
+    give the solo runs' results bit for bit."""
     B, solos, init, dts, ref, base = _launch_form_check([False])
     scratch = [f.clone() for f in init]          # the tuner advances the states it times
     ms = B.tune(scratch, dts, 1)

@@ -278,7 +278,8 @@ dg_status dg_batch_rk_step(dg_batch* b, void* const* f, const double* dt, int32_
  * for this batch: first the work-list order (cost-sorted or run-interleaved),
  * then, per kind (n, nv), its launch shape (a persistent grid of 1 to the
  * kind's occupancy limit work-groups per CU, or one work-group per tile),
- * one kind at a time, largest first.  The
+ * one kind at a time, largest first, then the other list order once more.
+ * The
  * per-kind grids are kept per (GPU arch, n, nv, FP32) for the life of the
  * process and start later batches.  Returns the
  * mean step time in ms of the choice; the states are advanced by the timed

@@ -8,15 +8,17 @@
 namespace dgk {
 
 // -------------------------------------------------------------------------
-// Batched persistent stage kernels: many independent runs (1D1V and 1D2V, n
-// in 2..12, FP32 storage).  The 1D2V runs are grouped by kind (n); each kind
-// gets one persistent launch per RK stage, specialised like the single-run
-// kernels (a single launch for every kind would carry the largest kind's
-// register allocation and run every kind at its occupancy).  The host
-// builds each kind's (run, tile) work list, ordered by decreasing tile cost
-// and split into 8 contiguous ranges, one per XCD; work-group b serves range
+// Batched stage kernels: many independent runs (1D1V and 1D2V, n in 2..12,
+// FP32 storage).  The 1D2V runs are grouped by kind (n); each kind gets one
+// launch per RK stage, specialised like the single-run kernels (a single
+// launch for every kind would carry the largest kind's register allocation
+// and run every kind at its occupancy).  The host builds each kind's (run,
+// tile) work list, ordered by decreasing tile cost (or run-interleaved) and
+// split into 8 contiguous ranges, one per XCD; work-group b serves range
 // b % 8 with a stride of the number of work-groups on that XCD, so the waves
-// of one XCD walk neighbouring tiles together.
+// of one XCD walk neighbouring tiles together.  The grid is the kind's
+// launch shape: persistent (a few work-groups per CU, each looping over its
+// range) or one work-group per tile.
 // The 1D1V runs of a batch, whatever their n, share one launch per stage (a
 // launch per n and stage costs a fixed ~10 us, often for ~1 % of the DOF;
 // inside a 1D2V kind's launch their latency-bound tiles ran slower still, at

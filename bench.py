@@ -23,7 +23,9 @@ The JSON line also carries
   sweep         -- the batched 64-run uneven sweep under the tuner's choice,
                    against its solo runs (--no-sweep skips it).
 --pattern-copy prints the copy references instead (streaming and tile-pattern
-copies of one state buffer next to the stage kernels).
+copies of one state buffer next to the stage kernels); --nn-step times the
+learned correction's corrected coarse step (fused and per-layer network);
+--write-traffic summarises two rocprofv3 counter runs into the traffic file.
 """
 import argparse
 import hashlib
@@ -258,6 +260,61 @@ def bench_sweep(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_nn_step(args):
+    """The learned correction's coarse step (coarse_1d2v_n4: 16^3 elements,
+    n = 4, omega_c = 0.05 as in the learned setting) with a random-init
+    network of the learned shape [7 n^3 + n, 128, 128, 128, n^3]: ms per
+    corrected SSP-RK3 step with the fused inference kernel and with one GEMM
+    launch per layer, next to the plain coarse step."""
+    import numpy as np
+    import torch
+    from paper_2202_13532_amd import dg
+    from paper_2202_13532_amd import workloads as W
+    wl = W.coarse_1d2v_n4(0.05)
+    s = dg.Solver(wl.nv, wl.n, wl.nelem, wl.lo, wl.hi, wl.omega_c)
+    f = make_state(torch, s, wl)
+    nfeat, nout = 7 * wl.n ** 3 + wl.n, wl.n ** 3
+    sizes = [nfeat, 128, 128, 128, nout]
+    rows = wl.nelem[0] * wl.nelem[1] * wl.nelem[2]
+    net = dg.Network(sizes, rows)
+    rng = np.random.default_rng(3)
+    ps = []
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        ps += [rng.standard_normal((a, b)) * math.sqrt(2.0 / a) * 0.1, rng.standard_normal(b) * 0.01]
+    net.set_params(dg.Network.flatten(ps))
+    mean = torch.zeros(nfeat, device="cuda")
+    inv = torch.ones(nfeat, device="cuda")
+    dt = wl.cfl_fraction * s.dt_max(max(float(s.poisson(f).abs().max()), 0.05))
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn(args.warmup)
+        torch.cuda.synchronize()
+        start.record()
+        fn(args.steps)
+        end.record()
+        torch.cuda.synchronize()
+        return start.elapsed_time(end) / args.steps
+
+    rec = {}
+    for fused in (True, False):
+        net.set_fused(fused)
+        g = f.clone()
+        rec["corrected_ms_" + ("fused" if fused else "layerwise")] = timed(
+            lambda k: dg.dg_nn_rk_step(s.ctx, net.nn, mean, inv, 1e-3, g, dt, k))
+    g = f.clone()
+    rec["plain_ms"] = timed(lambda k: s.step(g, dt, k))
+    dof = wl.dof()
+    line = {"metric": "corrected coarse SSP-RK3 step (learned correction)", "value": rec["corrected_ms_fused"],
+            "unit": "ms per step", "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "dtype": "f32 state, bf16 network", "data": "synthetic, random-init network",
+            "config": {"workload": wl.name, "dof": dof, "network": sizes, "rows": rows, "omega_c": wl.omega_c},
+            "nn_step": rec}
+    net.close()
+    s.close()
+    print(json.dumps(line), flush=True)
+
+
 def write_traffic(fetch_dir, write_dir, workload="maxwell_1d2v_n9"):
     """Summarise two rocprofv3 counter runs of `bench.py --copy-calibration`
     (one with FETCH_SIZE, one with WRITE_SIZE; their output directories) into
@@ -330,6 +387,8 @@ def main():
     ap.add_argument("--pattern-copy", action="store_true",
                     help="print the bandwidth of a streaming copy and of a copy with the stage kernel's tile "
                          "access pattern (no halos, no arithmetic) next to the stage kernels'")
+    ap.add_argument("--nn-step", action="store_true",
+                    help="time the learned correction's corrected coarse step (fused and per-layer network)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="summarise two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) into the traffic file; "
                          "runs nothing on the GPU")
@@ -343,6 +402,8 @@ def main():
 
     if args.workload == "uneven_sweep_64":
         return bench_sweep(args)
+    if args.nn_step:
+        return bench_nn_step(args)
 
     import torch
     from paper_2202_13532_amd import dg

@@ -335,8 +335,16 @@ int32_t dg_nn_input_ld(const dg_nn* nn);
 dg_status dg_nn_set_params(dg_nn* nn, const float* host_params);
 dg_status dg_nn_get_params(dg_nn* nn, float* host_params);
 /* Y (device, rows x out FP32) = network(X) for X (device, rows x input_ld
- * BF16); rows <= max_rows.                                                 */
+ * BF16); rows <= max_rows.  Networks of at most 8 layers with input width
+ * <= 1024 and every layer width <= 128 run as one fused launch (every
+ * layer's MFMA GEMM, bias and GELU per 16-row block, activations kept on
+ * chip); others one GEMM launch per layer.  The corrected steps use the
+ * same form.                                                               */
 dg_status dg_nn_forward(dg_nn* nn, const uint16_t* X, int32_t rows, float* Y);
+/* Inference form: on = 1 (default) the fused launch where the shape allows
+ * it, 0 one GEMM launch per layer (the form training uses).  Returns
+ * DG_ERR_UNSUPPORTED for on = 1 when the shape has no fused form.          */
+dg_status dg_nn_set_fused(dg_nn* nn, int32_t on);
 /* Forward + backward of the MSE loss mean((Y - T)^2) for targets T (device,
  * rows x out FP32); *loss receives the loss (host, waits); host_grads (may be
  * NULL) receives the gradient in the parameter-vector order.               */

@@ -37,6 +37,9 @@ struct NNLayout {
       off_Xf, off_Yo, off_corr, off_xm1, off_xm2, off_gpart, off_cpart, total;
   size_t gpart_floats = 0;   // split-K scratch of the GEMMs
   std::vector<size_t> off_A, off_Z;   // A[l]: BF16 input of layer l (l >= 1); Z[l]: pre-activation of layer l
+  std::vector<int> kp;                // K of layer l padded to a multiple of 32 (fused inference)
+  std::vector<size_t> off_Wt;         // layer l's weights transposed, out x kp BF16 (fused inference)
+  bool fusable = false;               // the shape fits the fused inference kernel
 };
 
 const char* nn_validate(const int32_t* sizes, int32_t nlayers, int32_t max_rows) {
@@ -94,6 +97,12 @@ NNLayout nn_layout(const int32_t* sizes, int32_t nlayers, int32_t max_rows) {
   N.gpart_floats = std::max(4 * R * static_cast<size_t>(N.wmax), 32 * wmm);
   N.off_gpart = take(N.gpart_floats * 4);
   N.off_cpart = take(static_cast<size_t>(dgn::kColsumPart) * N.wmax * 4);
+  N.fusable = nlayers <= dgn::kMlpMaxLayers && ((sizes[0] + 31) / 32) * 32 <= dgn::kMlpMaxIn;
+  for (int l = 0; l < nlayers; ++l) {
+    N.kp.push_back((sizes[l] + 31) / 32 * 32);
+    if (sizes[l + 1] > dgn::kMlpMaxOut) N.fusable = false;
+  }
+  for (int l = 0; l < nlayers; ++l) N.off_Wt.push_back(N.fusable ? take(static_cast<size_t>(sizes[l + 1]) * N.kp[l] * 2) : 0);
   N.total = o;
   return N;
 }
@@ -177,6 +186,8 @@ struct dg_nn {
   int cus = 256;   // compute units of the device (split-K sizing)
   int64_t t = 0;   // AdamW step count
   bool have_grads = false;
+  bool wt_stale = true;   // the transposed weight copies lag the parameters
+  bool fused = true;      // inference through the fused kernel when the shape fits
   std::string err = "no error";
   // cached graph of one corrected coarse step and what it was captured for
   hipGraphExec_t gexec = nullptr;
@@ -254,6 +265,42 @@ dg_status forward_on(dg_nn* nn, const uint16_t* X, int rows, float* Y, bool keep
     NN_HIP(nn, run_gemm(nn, g, s));
     if (!last) A = nn->at<uint16_t>(N.off_A[l + 1]);
   }
+  return DG_OK;
+}
+
+// Transposed BF16 weight copies for the fused kernel, if the parameters
+// changed since they were made (enqueued on s).
+dg_status refresh_wt(dg_nn* nn, hipStream_t s) {
+  const NNLayout& N = nn->N;
+  if (!N.fusable || !nn->wt_stale) return DG_OK;
+  for (int l = 0; l < N.L; ++l)
+    NN_HIP(nn, dgn::launch_transpose_weights(nn->at<uint16_t>(N.off_Pbf) + N.offW[l], N.sizes[l], N.sizes[l + 1], N.kp[l],
+                                             nn->at<uint16_t>(N.off_Wt[l]), s));
+  nn->wt_stale = false;
+  return DG_OK;
+}
+
+// Inference Y = NN(X): one fused launch when the shape fits (and fused
+// inference is on), else one GEMM launch per layer.  The transposed weights
+// must be current (refresh_wt).
+dg_status forward_infer(dg_nn* nn, const uint16_t* X, int rows, float* Y, hipStream_t s) {
+  const NNLayout& N = nn->N;
+  if (!N.fusable || !nn->fused) return forward_on(nn, X, rows, Y, false, s);
+  if (nn->wt_stale) return nfail(nn, DG_ERR_INVALID, "internal: transposed weights are stale");
+  dgn::MlpArgs a{};
+  a.X = X;
+  a.ldx = N.ld[0];
+  a.rows = rows;
+  a.L = N.L;
+  for (int l = 0; l < N.L; ++l) {
+    a.in[l] = N.sizes[l];
+    a.out[l] = N.sizes[l + 1];
+    a.kp[l] = N.kp[l];
+    a.Wt[l] = nn->at<uint16_t>(N.off_Wt[l]);
+    a.bias[l] = nn->at<float>(N.off_P) + N.offb[l];
+  }
+  a.Y = Y;
+  NN_HIP(nn, dgn::launch_mlp_fused(a, s));
   return DG_OK;
 }
 
@@ -390,6 +437,7 @@ dg_status dg_nn_set_params(dg_nn* nn, const float* host_params) {
   NN_HIP(nn, hipStreamSynchronize(nn->stream));
   nn->t = 0;
   nn->have_grads = false;
+  nn->wt_stale = true;
   return DG_OK;
 }
 
@@ -405,7 +453,23 @@ dg_status dg_nn_forward(dg_nn* nn, const uint16_t* X, int32_t rows, float* Y) {
   if (!nn) return DG_ERR_INVALID;
   if (!X || !Y) return nfail(nn, DG_ERR_INVALID, "X and Y must be non-NULL");
   NN_TRY(check_rows(nn, rows));
-  return forward_on(nn, X, rows, Y, false, nn->stream);
+  NN_TRY(refresh_wt(nn, nn->stream));
+  return forward_infer(nn, X, rows, Y, nn->stream);
+}
+
+dg_status dg_nn_set_fused(dg_nn* nn, int32_t on) {
+  if (!nn) return DG_ERR_INVALID;
+  if (on != 0 && on != 1) return nfail(nn, DG_ERR_INVALID, "dg_nn_set_fused: on must be 0 or 1");
+  if ((on != 0) != nn->fused) {
+    nn->fused = on != 0;
+    // a cached corrected step holds the other form
+    if (nn->gexec) {
+      (void)hipDeviceSynchronize();
+      (void)hipGraphExecDestroy(nn->gexec);
+      nn->gexec = nullptr;
+    }
+  }
+  return nn->N.fusable || on == 0 ? DG_OK : nfail(nn, DG_ERR_UNSUPPORTED, "this network's shape has no fused form");
 }
 
 dg_status dg_nn_loss_grad(dg_nn* nn, const uint16_t* X, const float* T, int32_t rows, double* loss, float* host_grads) {
@@ -481,6 +545,7 @@ dg_status dg_nn_adamw(dg_nn* nn, float lr, float weight_decay) {
       NN_HIP(nn, dgn::launch_adamw(a, nn->stream));
     }
   }
+  nn->wt_stale = true;
   return DG_OK;
 }
 
@@ -704,7 +769,7 @@ dg_status corrected_stage(dg_ctx* c, dg_nn* nn, const float* mean, const float* 
   if (e == hipSuccess) e = dgn::launch_gather(gather_args(c, fin, E, mean, inv_std, Xf, nn->N.ld[0], xm_f), s);
   if (e != hipSuccess) return dgi::hip_fail(c, e, "gather launch");
   {
-    dg_status st = forward_on(nn, Xf, rows, Yo, false, s);
+    dg_status st = forward_infer(nn, Xf, rows, Yo, s);
     if (st != DG_OK) return dgi::fail(c, st, nn->err);
   }
   dgn::ScatterArgs sc{};
@@ -794,7 +859,9 @@ dg_status dg_nn_rk_step(dg_ctx* coarse, dg_nn* nn, const float* mean, const floa
   if (const char* why = coarse_mismatch(coarse, nn)) return dgi::fail(coarse, DG_ERR_INVALID, why);
   if (!std::isfinite(out_scale)) return dgi::fail(coarse, DG_ERR_INVALID, "out_scale must be finite");
   if (nsteps == 0 && f && dt > 0.0) return DG_OK;
-  // order after the network's stream (parameter updates) as well
+  // transposed weights for the fused network, then order after the network's
+  // stream (parameter updates, that refresh) as well
+  if (dg_status st = refresh_wt(nn, nn->stream); st != DG_OK) return dgi::fail(coarse, st, nn->err);
   hipError_t e = hipEventRecord(nn->ev, nn->stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(coarse->stream, nn->ev, 0);
   if (e != hipSuccess) return dgi::hip_fail(coarse, e, "network stream ordering");

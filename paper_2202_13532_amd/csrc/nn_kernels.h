@@ -60,6 +60,23 @@ struct AdamArgs {
   float lr, b1, b2, eps, wd, c1, c2;   // c1 = 1 - b1^t, c2 = 1 - b2^t
 };
 
+// Whole-network inference in one launch: every layer's GEMM, bias and GELU
+// for RM rows per work-group, activations kept in LDS.  Shapes: at most
+// kMlpMaxLayers layers, input width <= kMlpMaxIn, every layer output <= kMlpMaxOut.
+constexpr int kMlpMaxLayers = 8, kMlpMaxIn = 1024, kMlpMaxOut = 128;
+struct MlpArgs {
+  const uint16_t* X;                  // rows x ldx BF16 inputs (columns >= in[0] are zero)
+  int ldx, rows, L;
+  int in[kMlpMaxLayers], out[kMlpMaxLayers];
+  int kp[kMlpMaxLayers];              // K padded to a multiple of 32
+  const uint16_t* Wt[kMlpMaxLayers];  // out x kp BF16: W transposed, zero for k >= in
+  const float* bias[kMlpMaxLayers];
+  float* Y;                           // rows x out[L-1] FP32 (no GELU on the last layer)
+};
+hipError_t launch_mlp_fused(const MlpArgs& a, hipStream_t s);
+// Wt[n * kp + k] = W[k * out + n] for k < in, 0 for in <= k < kp (BF16)
+hipError_t launch_transpose_weights(const uint16_t* W, int in, int out, int kp, uint16_t* Wt, hipStream_t s);
+
 hipError_t launch_project_axis(const ProjArgs& a, hipStream_t s);
 hipError_t launch_f32_to_f64(const float* in, double* out, size_t n, hipStream_t s);
 hipError_t launch_f64_to_f32(const double* in, float* out, size_t n, hipStream_t s);

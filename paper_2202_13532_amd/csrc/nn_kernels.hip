@@ -357,6 +357,166 @@ __global__ void __launch_bounds__(256) gemm_bf16_tiled_kernel(GemmArgs g, float*
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference: a work-group of kMlpWaves waves takes kMlpRows rows
+// through every layer.  The input rows are staged in LDS (k contiguous, zero
+// beyond ldx); each layer's 16-column output tiles are dealt round-robin to
+// the waves (one each at width 128: the per-wave chain of dependent
+// instructions is what bounds this latency-bound kernel),
+// each tile's B operand read straight from the transposed weights (8 k
+// values of one column = one 16-byte load).  The weights do not depend on
+// the activations, so their loads are not left on the critical path: layer
+// 0's (its k range up to kMlpKT0 tiles) go out before the input staging,
+// and each hidden layer's (at most kMlpMaxOut / 32 k tiles) while the layer
+// before it computes.  The epilogue adds the bias, applies GELU (hidden
+// layers) and writes the BF16 activations to the other LDS buffer, or the
+// FP32 outputs (last layer).  One row tile of 16: the weights are read once
+// per work-group, from L2, and 16-row work-groups spread a few thousand rows
+// over all CUs.
+// ---------------------------------------------------------------------------
+constexpr int kMlpRows = 16, kMlpWaves = 8, kMlpThreads = 64 * kMlpWaves;
+constexpr int kMlpTilesPerWave = (kMlpMaxOut / 16 + kMlpWaves - 1) / kMlpWaves;
+constexpr int kMlpKT0 = 16;                  // layer-0 k tiles held in registers (inputs <= 512 in one pass)
+constexpr int kMlpXB = 4;                    // input-staging loads in flight per thread
+constexpr int kMlpKTH = kMlpMaxOut / 32;     // k tiles of a hidden layer
+constexpr int kMlpHLd = kMlpMaxOut + 8;      // hidden LDS row (BF16), padded against bank conflicts
+constexpr int kMlpXLd = kMlpMaxIn + 8;
+
+// B operand of k tile kt for the wave's tile j of a layer (zero where the
+// column or k tile is out of range)
+__device__ __forceinline__ bf16x8 mlp_b(const uint16_t* Wt, int kp, int out, int ntiles, int wave, int j, int kt, int nkt,
+                                       int lane) {
+  const int col = (wave + kMlpWaves * j) * 16 + (lane & 15);
+  if (wave + kMlpWaves * j >= ntiles || col >= out || kt >= nkt) return bf16x8{};
+  return *reinterpret_cast<const bf16x8*>(Wt + static_cast<size_t>(col) * kp + 32 * kt + 8 * (lane >> 4));
+}
+
+__global__ void __launch_bounds__(kMlpThreads) mlp_fused_kernel(MlpArgs a) {
+  __shared__ uint16_t Xs[kMlpRows * kMlpXLd];
+  __shared__ uint16_t Hs[2][kMlpRows * kMlpHLd];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * kMlpRows;
+  // layer-0 weights (first kMlpKT0 k tiles) first: the longest loads
+  bf16x8 b0[kMlpTilesPerWave][kMlpKT0];
+  {
+    const int nkt = a.kp[0] / 32, nt = (a.out[0] + 15) / 16;
+#pragma unroll
+    for (int j = 0; j < kMlpTilesPerWave; ++j)
+#pragma unroll
+      for (int q = 0; q < kMlpKT0; ++q) b0[j][q] = mlp_b(a.Wt[0], a.kp[0], a.out[0], nt, wave, j, q, nkt, lane);
+  }
+  // input rows, 8 BF16 per thread and load, kMlpXB loads in flight, zero
+  // past the row's end
+  const int kp0 = a.kp[0], xtot = kMlpRows * kp0;
+  for (int e0 = tid * 8; e0 < xtot; e0 += kMlpThreads * 8 * kMlpXB) {
+    uint4 v[kMlpXB];
+#pragma unroll
+    for (int i = 0; i < kMlpXB; ++i) {
+      const int e = e0 + kMlpThreads * 8 * i, r = e / kp0, k = e % kp0, m = m0 + r;
+      v[i] = (e < xtot && m < a.rows) ? load8v(a.X + static_cast<size_t>(m) * a.ldx, k, a.ldx) : uint4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < kMlpXB; ++i) {
+      const int e = e0 + kMlpThreads * 8 * i, r = e / kp0, k = e % kp0;
+      if (e < xtot) *reinterpret_cast<uint4*>(&Xs[r * kMlpXLd + k]) = v[i];
+    }
+  }
+  __syncthreads();
+  bf16x8 bh[kMlpTilesPerWave][kMlpKTH];   // the current hidden layer's weights
+  for (int l = 0; l < a.L; ++l) {
+    const uint16_t* As = l == 0 ? Xs : Hs[(l - 1) & 1];
+    const int lda = l == 0 ? kMlpXLd : kMlpHLd;
+    const int out = a.out[l], kp = a.kp[l], nkt = kp / 32;
+    const bool last = l == a.L - 1;
+    const int ntiles = (out + 15) / 16;
+    // next layer's weights, in flight while this layer computes
+    bf16x8 bnext[kMlpTilesPerWave][kMlpKTH];
+    if (!last) {
+      const int kpn = a.kp[l + 1], ntn = (a.out[l + 1] + 15) / 16;
+#pragma unroll
+      for (int j = 0; j < kMlpTilesPerWave; ++j)
+#pragma unroll
+        for (int q = 0; q < kMlpKTH; ++q) bnext[j][q] = mlp_b(a.Wt[l + 1], kpn, a.out[l + 1], ntn, wave, j, q, kpn / 32, lane);
+    }
+    const uint16_t* arow = As + (lane & 15) * lda + 8 * (lane >> 4);
+    f32x4 acc[kMlpTilesPerWave];
+#pragma unroll
+    for (int j = 0; j < kMlpTilesPerWave; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    if (l == 0) {
+#pragma unroll
+      for (int q = 0; q < kMlpKT0; ++q) {
+        if (q < nkt) {   // uniform
+          const bf16x8 af = *reinterpret_cast<const bf16x8*>(arow + 32 * q);
+#pragma unroll
+          for (int j = 0; j < kMlpTilesPerWave; ++j)
+            if (wave + kMlpWaves * j < ntiles) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b0[j][q], acc[j], 0, 0, 0);
+        }
+      }
+      // inputs wider than kMlpKT0 k tiles: the rest, loaded as it is used
+      for (int q = kMlpKT0; q < nkt; ++q) {
+        const bf16x8 af = *reinterpret_cast<const bf16x8*>(arow + 32 * q);
+#pragma unroll
+        for (int j = 0; j < kMlpTilesPerWave; ++j)
+          if (wave + kMlpWaves * j < ntiles)
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, mlp_b(a.Wt[0], kp, out, ntiles, wave, j, q, nkt, lane),
+                                                             acc[j], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < kMlpKTH; ++q) {
+        if (q < nkt) {   // uniform
+          const bf16x8 af = *reinterpret_cast<const bf16x8*>(arow + 32 * q);
+#pragma unroll
+          for (int j = 0; j < kMlpTilesPerWave; ++j)
+            if (wave + kMlpWaves * j < ntiles) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bh[j][q], acc[j], 0, 0, 0);
+        }
+      }
+    }
+    // epilogue: D column lane % 16, rows 4 (lane / 16) + t
+    uint16_t* Hn = Hs[l & 1];
+    const int kpn = last ? 0 : a.kp[l + 1];
+#pragma unroll
+    for (int j = 0; j < kMlpTilesPerWave; ++j) {
+      const int col = (wave + kMlpWaves * j) * 16 + (lane & 15);
+      if (wave + kMlpWaves * j >= ntiles) continue;
+      const float b = col < out ? a.bias[l][col] : 0.0f;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = 4 * (lane >> 4) + t, m = m0 + r;
+        const float z = acc[j][t] + b;
+        if (last) {
+          if (m < a.rows && col < out) a.Y[static_cast<size_t>(m) * out + col] = z;
+        } else if (col < kpn) {
+          // zero in the padding columns: the next layer reads k up to kp
+          Hn[r * kMlpHLd + col] = col < out ? f2bf(gelu(z)) : uint16_t(0);
+        }
+      }
+    }
+    // padding columns of the next layer's input beyond the last output tile
+    if (!last) {
+      if (ntiles * 16 < kpn) {   // uniform: only when out is not a multiple of 16 below kpn
+        for (int e = tid; e < kMlpRows * kpn; e += kMlpThreads) {
+          const int r = e / kpn, k = e % kpn;
+          if (k >= ntiles * 16) Hn[r * kMlpHLd + k] = 0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kMlpTilesPerWave; ++j)
+#pragma unroll
+        for (int q = 0; q < kMlpKTH; ++q) bh[j][q] = bnext[j][q];
+    }
+    __syncthreads();
+  }
+}
+
+// Wt[n * kp + k] = W[k * out + n] (zero for k >= in).
+__global__ void transpose_weights_kernel(const uint16_t* W, int in, int out, int kp, uint16_t* Wt) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<size_t>(out) * kp) return;
+  const int n = static_cast<int>(i / kp), k = static_cast<int>(i % kp);
+  Wt[i] = k < in ? W[static_cast<size_t>(k) * out + n] : uint16_t(0);
+}
+
 // C(m, n) = sum over the slices in order.
 __global__ void gemm_reduce_kernel(const float* part, int slices, GemmArgs g) {
   const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -745,6 +905,25 @@ hipError_t launch_to_elements64(const double* in, const double* sub, const doubl
 }
 hipError_t launch_xmean(const float* in, const double* wx, float* out, int outer, size_t inner, hipStream_t s) {
   hipLaunchKernelGGL(xmean_kernel, dim3(nblk(inner, 256)), dim3(256), 0, s, in, wx, out, outer, inner);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_fused(const MlpArgs& a, hipStream_t s) {
+  if (a.L < 1 || a.L > kMlpMaxLayers || a.rows < 1 || a.kp[0] > kMlpMaxIn) return hipErrorInvalidValue;
+  for (int l = 0; l < a.L; ++l) {
+    if (a.out[l] < 1 || a.out[l] > kMlpMaxOut || a.kp[l] % 32 || a.kp[l] < a.in[l]) return hipErrorInvalidValue;
+    if (l > 0 && (a.in[l] != a.out[l - 1] || a.kp[l] > kMlpMaxOut)) return hipErrorInvalidValue;
+  }
+  const int blocks = (a.rows + kMlpRows - 1) / kMlpRows;
+  hipLaunchKernelGGL(mlp_fused_kernel, dim3(blocks), dim3(kMlpThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_weights(const uint16_t* W, int in, int out, int kp, uint16_t* Wt, hipStream_t s) {
+  const size_t total = static_cast<size_t>(out) * kp;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(transpose_weights_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, W, in, out,
+                     kp, Wt);
   return hipGetLastError();
 }
 

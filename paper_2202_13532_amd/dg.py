@@ -28,7 +28,7 @@ EXPORTED = ["dg_workspace_bytes", "dg_init", "dg_destroy", "dg_rhs", "dg_poisson
             "dg_projection_matrix", "dg_project", "dg_nn_features", "dg_nn_features_raw", "dg_nn_to_elements",
             "dg_nn_column_stats", "dg_nn_rk_step", "dg_nn_last_error", "dg_state_elems", "dg_state_pack",
             "dg_state_unpack", "dg_rhs_static", "dg_set_background", "dg_fourier", "dg_filter_x",
-            "dg_profile_copy", "dg_batch_choice", "dg_batch_set_choice"]
+            "dg_profile_copy", "dg_batch_choice", "dg_batch_set_choice", "dg_nn_set_fused"]
 
 
 class dg_config(ctypes.Structure):
@@ -100,6 +100,7 @@ def lib():
         "dg_nn_set_params": (I, [P, fp]),
         "dg_nn_get_params": (I, [P, fp]),
         "dg_nn_forward": (I, [P, P, I, P]),
+        "dg_nn_set_fused": (I, [P, I]),
         "dg_nn_loss_grad": (I, [P, P, P, I, dp, fp]),
         "dg_nn_adamw": (I, [P, ctypes.c_float, ctypes.c_float]),
         "dg_projection_matrix": (I, [I, I, I, dp]),
@@ -613,6 +614,10 @@ def dg_nn_forward(nn, X, rows, Y):
     _ncheck(lib().dg_nn_forward(nn, _ptr(X), int(rows), _ptr(Y)), nn)
 
 
+def dg_nn_set_fused(nn, on):
+    _ncheck(lib().dg_nn_set_fused(nn, 1 if on else 0), nn)
+
+
 def dg_nn_loss_grad(nn, X, T, rows, want_loss=True, want_grads=False):
     loss = np.zeros(1)
     g = np.zeros(dg_nn_param_count(nn), dtype=np.float32) if want_grads else None
@@ -716,15 +721,30 @@ class Network:
 
     def _rows(self, X):
         t = self.torch
-        if X.dtype != t.int16 or X.dim() != 2 or X.shape[1] != self.ld or not X.is_contiguous():
-            raise DGError(DG_ERR_INVALID, "X must be contiguous int16 (BF16 bits) of shape (rows, %d)" % self.ld)
+        if (not isinstance(X, t.Tensor) or X.device.type != "cuda" or X.dtype != t.int16 or X.dim() != 2
+                or X.shape[1] != self.ld or not X.is_contiguous()):
+            raise DGError(DG_ERR_INVALID, "X must be a contiguous int16 (BF16 bits) device tensor of shape (rows, %d)"
+                          % self.ld)
         return X.shape[0]
 
     def forward(self, X, out=None):
         rows = self._rows(X)
-        Y = self.torch.empty((rows, self.sizes[-1]), dtype=self.torch.float32, device=self.device) if out is None else out
+        t = self.torch
+        if out is None:
+            Y = t.empty((rows, self.sizes[-1]), dtype=t.float32, device=self.device)
+        else:
+            if (not isinstance(out, t.Tensor) or out.device.type != "cuda" or out.dtype != t.float32
+                    or tuple(out.shape) != (rows, self.sizes[-1]) or not out.is_contiguous()):
+                raise DGError(DG_ERR_INVALID, "out must be a contiguous float32 device tensor of shape (%d, %d)"
+                              % (rows, self.sizes[-1]))
+            Y = out
         dg_nn_forward(self.nn, X, rows, Y)
         return Y
+
+    def set_fused(self, on):
+        """Inference form: the fused single launch (default, where the shape
+        allows it) or one GEMM launch per layer."""
+        dg_nn_set_fused(self.nn, on)
 
     def loss_grad(self, X, T, want_loss=True, want_grads=False):
         rows = self._rows(X)

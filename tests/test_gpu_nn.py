@@ -2,7 +2,10 @@
 
 * MFMA GEMM: integer-valued BF16 operands make every product and partial sum
   exact in FP32, so a one-layer network X W + b must equal the integer matmul
-  bit for bit (ragged rows, inputs and outputs).
+  bit for bit (ragged rows, inputs and outputs), through the fused inference
+  kernel and through the per-layer GEMM.
+* Fused inference: against the per-layer form and the FP64 oracle MLP, and
+  after parameter updates.
 * Forward / gradients: against the FP64 oracle MLP evaluated on the same
   BF16-rounded inputs and weights.  The device rounds every hidden activation
   and back-propagated gradient to BF16 (unit roundoff 2^-9 = 1.95e-3); over
@@ -76,14 +79,19 @@ def _cos(a, b):
 
 
 # (16384, 452, 128) takes the 64-row tiles, the others the 32-row tiles
-@pytest.mark.parametrize("rows,k,n", [(37, 40, 24), (1000, 452, 128), (4133, 128, 64), (5, 3, 1), (16384, 452, 128)])
-def test_mfma_gemm_exact_on_integer_operands(rows, k, n):
-    print("gemm exact", rows, k, n, flush=True)
+# fused: the whole-network kernel (one 16-row block per work-group, weights
+# transposed); else the per-layer GEMM
+@pytest.mark.parametrize("fused", [True, False], ids=["fused", "layerwise"])
+@pytest.mark.parametrize("rows,k,n", [(37, 40, 24), (1000, 452, 128), (4133, 128, 64), (5, 3, 1), (16384, 452, 128),
+                                      (77, 1000, 100)])
+def test_mfma_gemm_exact_on_integer_operands(rows, k, n, fused):
+    print("gemm exact", rows, k, n, fused, flush=True)
     rng = np.random.default_rng(rows + k + n)
     X = rng.integers(-4, 5, size=(rows, k)).astype(np.float32)
     W = rng.integers(-3, 4, size=(k, n)).astype(np.float32)
     b = rng.integers(-8, 9, size=n).astype(np.float32)
     net = dg.Network([k, n], rows)
+    net.set_fused(fused)
     net.set_params(dg.Network.flatten([W, b]))
     Xd, _ = _x_tensor(X, net.ld)
     Y = net.forward(Xd).cpu().numpy()
@@ -117,6 +125,64 @@ def test_weight_gradient_gemm_exact_on_integer_operands(rows, k, n):
 
 
 SIZES = [452, 128, 128, 128, 64]
+
+
+@pytest.mark.parametrize("sizes", [SIZES, [516, 128, 128, 128, 64], [100, 50, 70, 10], [33, 128, 1]],
+                         ids=lambda z: "x".join(map(str, z)))
+def test_fused_forward_matches_layerwise_and_oracle(sizes):
+    """The fused inference kernel against the per-layer GEMMs (same BF16
+    weights and activations, another FP32 summation order: a BF16 rounding of
+    a hidden activation can flip, so relative L2 <= 5e-3, cosine >= 0.99999)
+    and both against the FP64 oracle MLP (the BF16 bar above); ragged rows
+    and widths that are not multiples of 16 or 32."""
+    rows = 4133
+    print("fused forward", sizes, rows, flush=True)
+    rng = np.random.default_rng(sum(sizes))
+    ps = _he_params(sizes, 5)
+    net = dg.Network(sizes, rows)
+    net.set_params(dg.Network.flatten(ps))
+    Xd, Xv = _x_tensor(rng.standard_normal((rows, sizes[0])), net.ld)
+    y_fused = net.forward(Xd).cpu().numpy().astype(np.float64)
+    net.set_fused(False)
+    y_layer = net.forward(Xd).cpu().numpy().astype(np.float64)
+    y_ref, _ = mlp.forward(_round_weights(ps), Xv)
+    assert _rel_l2(y_fused, y_layer) <= 5e-3 and _cos(y_fused, y_layer) >= 0.99999
+    for y in (y_fused, y_layer):
+        assert _rel_l2(y, y_ref) < 2e-2 and _cos(y, y_ref) > 0.999
+    net.close()
+
+
+def test_fused_forward_follows_parameter_updates():
+    """The transposed weights of the fused kernel are refreshed after
+    set_params and after AdamW steps: the fused and per-layer forms agree
+    again after each update."""
+    rows = 500
+    sizes = [40, 32, 16]
+    rng = np.random.default_rng(9)
+    net = dg.Network(sizes, rows)
+    net.set_params(dg.Network.flatten(_he_params(sizes, 1)))
+    Xd, _ = _x_tensor(rng.standard_normal((rows, sizes[0])), net.ld)
+    Td = torch.from_numpy(rng.standard_normal((rows, sizes[-1])).astype(np.float32)).cuda()
+
+    def both():
+        net.set_fused(True)
+        a = net.forward(Xd).cpu().numpy().astype(np.float64)
+        net.set_fused(False)
+        b = net.forward(Xd).cpu().numpy().astype(np.float64)
+        net.set_fused(True)
+        return a, b
+
+    a0, b0 = both()
+    assert _rel_l2(a0, b0) <= 5e-3
+    net.set_params(dg.Network.flatten(_he_params(sizes, 2)))
+    a1, b1 = both()
+    assert _rel_l2(a1, b1) <= 5e-3 and _rel_l2(a1, a0) > 0.1
+    for _ in range(3):
+        net.loss_grad(Xd, Td, want_loss=False, want_grads=True)
+        net.adamw(1e-2, 0.0)
+    a2, b2 = both()
+    assert _rel_l2(a2, b2) <= 5e-3 and _rel_l2(a2, a1) > 1e-3
+    net.close()
 
 
 def test_forward_and_gradients_match_oracle():

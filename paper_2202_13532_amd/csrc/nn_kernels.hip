@@ -104,17 +104,10 @@ __global__ void f64_to_f32_kernel(const double* in, float* out, size_t n) {
 // One thread per (row, column); 32-bit index arithmetic (launch_gather checks
 // that rows x ld and the state size fit).
 // ---------------------------------------------------------------------------
-__global__ void gather_kernel(GatherArgs a) {
+// Feature `col` of the row of element (ix, iu, iv), normalised (0 for
+// padding columns).
+__device__ __forceinline__ float gather_value(const GatherArgs& a, int ix, int iu, int iv, int col) {
   const int n = a.n, nb = n * n * n;
-  const unsigned total = static_cast<unsigned>(a.Nx) * a.Nu * a.Nv * a.ld;
-  const unsigned tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= total) return;
-  const int col = static_cast<int>(tid % static_cast<unsigned>(a.ld));
-  const unsigned e = tid / static_cast<unsigned>(a.ld);
-  const int iv = static_cast<int>(e % static_cast<unsigned>(a.Nv));
-  const unsigned e2 = e / static_cast<unsigned>(a.Nv);
-  const int iu = static_cast<int>(e2 % static_cast<unsigned>(a.Nu));
-  const int ix = static_cast<int>(e2 / static_cast<unsigned>(a.Nu));
   float val = 0.0f;
   if (col < 7 * nb) {
     const int blk = col / nb, loc = col % nb;
@@ -139,9 +132,20 @@ __global__ void gather_kernel(GatherArgs a) {
     const int ju = (loc / n) % n, jv = loc % n;
     val = a.xmean[((static_cast<unsigned>(iu) * n + ju) * a.Nv + iv) * n + jv];
   }
-  const bool real = col < a.nfeat;
-  const float z = real ? (val - a.mean[col]) * a.inv_std[col] : 0.0f;
-  a.X[tid] = f2bf(z);
+  return col < a.nfeat ? (val - a.mean[col]) * a.inv_std[col] : 0.0f;
+}
+
+__global__ void gather_kernel(GatherArgs a) {
+  const unsigned total = static_cast<unsigned>(a.Nx) * a.Nu * a.Nv * a.ld;
+  const unsigned tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= total) return;
+  const int col = static_cast<int>(tid % static_cast<unsigned>(a.ld));
+  const unsigned e = tid / static_cast<unsigned>(a.ld);
+  const int iv = static_cast<int>(e % static_cast<unsigned>(a.Nv));
+  const unsigned e2 = e / static_cast<unsigned>(a.Nv);
+  const int iu = static_cast<int>(e2 % static_cast<unsigned>(a.Nu));
+  const int ix = static_cast<int>(e2 / static_cast<unsigned>(a.Nu));
+  a.X[tid] = f2bf(gather_value(a, ix, iu, iv, col));
 }
 
 // Network output Y[e][loc] (loc = (jx*n + ju)*n + jv), scaled by `scale`,
@@ -910,6 +914,7 @@ hipError_t launch_xmean(const float* in, const double* wx, float* out, int outer
 
 hipError_t launch_mlp_fused(const MlpArgs& a, hipStream_t s) {
   if (a.L < 1 || a.L > kMlpMaxLayers || a.rows < 1 || a.kp[0] > kMlpMaxIn) return hipErrorInvalidValue;
+  if (!a.X || a.ldx < a.in[0]) return hipErrorInvalidValue;
   for (int l = 0; l < a.L; ++l) {
     if (a.out[l] < 1 || a.out[l] > kMlpMaxOut || a.kp[l] % 32 || a.kp[l] < a.in[l]) return hipErrorInvalidValue;
     if (l > 0 && (a.in[l] != a.out[l - 1] || a.kp[l] > kMlpMaxOut)) return hipErrorInvalidValue;

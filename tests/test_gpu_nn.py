@@ -495,6 +495,37 @@ def test_corrected_step_matches_oracle(scale, fluct):
     net.close()
 
 
+@pytest.mark.parametrize("fluct", [False, True])
+def test_corrected_step_fused_equals_layerwise(fluct):
+    """One corrected step with the fused network against one GEMM launch per
+    layer: the same features, the network summed in another order (BF16
+    activations can flip), so the two increments agree to relative L2 5e-3."""
+    n, nelem = 4, [5, 4, 6]
+    lo, hi = [0.0, -6.0, -6.0], [4 * math.pi, 6.0, 6.0]
+    s = dg.Solver(2, n, nelem, lo, hi, 1.0)
+    g = grid.PhaseGrid(2, n, nelem, lo, hi, 1.0)
+    c = g.coords()
+    f0 = torch.from_numpy(inputs.mixture(c[0], c[1], c[2], 0.5, 1.0, 0.5, 0.05, 3.0)).float().cuda()
+    nfeat = (8 if fluct else 7) * n ** 3 + n
+    sizes = [nfeat, 128, 128, 128, n ** 3]
+    net = dg.Network(sizes, 5 * 4 * 6)
+    ps = _he_params(sizes, 12)
+    ps[-2] = ps[-2] * 0.01
+    ps[-1] = ps[-1] * 0.01
+    net.set_params(dg.Network.flatten(ps))
+    mean = torch.zeros(nfeat, device="cuda")
+    inv = torch.full((nfeat,), 3.0, device="cuda")
+    dt = 0.5 * s.dt_max(float(s.poisson(f0).abs().max()))
+    out = {}
+    for fused in (True, False):
+        net.set_fused(fused)
+        f = f0.clone()
+        dg.dg_nn_rk_step(s.ctx, net.nn, mean, inv, 1.0, f, dt, 1)
+        out[fused] = (f - f0).cpu().numpy().astype(np.float64)
+    assert _rel_l2(out[True], out[False]) < 5e-3
+    net.close()
+
+
 def test_corrected_step_graph_replays_match_separate_calls():
     """The corrected step is replayed from a captured graph: three replays in
     one call must equal three one-step calls (each with its own eager field

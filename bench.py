@@ -331,8 +331,10 @@ def write_traffic(fetch_dir, write_dir, workload="maxwell_1d2v_n9"):
                 acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
         return acc
 
+    import re
+
     def find(acc, key):
-        ks = [k for k in acc if key in k]
+        ks = [k for k in acc if re.search(key, k)]
         if len(ks) != 1:
             raise SystemExit("expected one kernel matching %r, found %s" % (key, ks))
         return acc[ks[0]]
@@ -341,8 +343,11 @@ def write_traffic(fetch_dir, write_dir, workload="maxwell_1d2v_n9"):
     dof = wl.dof()
     F, W = per_kernel(fetch_dir), per_kernel(write_dir)
     n = wl.n
-    s1f, s23f = find(F, "stage2v_kernel<float, %d, false, false>" % n), find(F, "stage2v_kernel<float, %d, true, false>" % n)
-    s1w, s23w = find(W, "stage2v_kernel<float, %d, false, false>" % n), find(W, "stage2v_kernel<float, %d, true, false>" % n)
+    # the plain stage kernels (template arguments T, n, UN, BG[, CORR])
+    k1 = r"stage2v_kernel<float, %d, false, false(, false)?>" % n
+    k23 = r"stage2v_kernel<float, %d, true, false(, false)?>" % n
+    s1f, s23f = find(F, k1), find(F, k23)
+    s1w, s23w = find(W, k1), find(W, k23)
     # the calibration copies: the large copyBuffer dispatches
     cf = [v for v in find(F, "copyBuffer") if v > 1e5]
     cw = [v for v in find(W, "copyBuffer") if v > 1e5]

@@ -214,8 +214,22 @@ void fill_pack(const dg_ctx* c, dgk::StageArgs<T>* p, const void* fin, const voi
 
 // One fused stage kernel: out = c_un un + c_in fin + c_dt L(fin) (L with field E).
 dg_status stage(dg_ctx* c, const void* fin, const void* fun, void* out, const double* E,
-                double* partials, double c_un, double c_in, double c_dt, bool reverse) {
+                double* partials, double c_un, double c_in, double c_dt, bool reverse, const float* corr,
+                const float* corr_xm) {
   hipError_t e;
+  if (corr) {
+    // the corrected stage of the learned correction: FP32, 1D2V, dense rows, whole f
+    if (c->f64() || c->cfg.nv != 2 || c->cfg.layout != DG_LAYOUT_DENSE || c->bg)
+      return fail(c, DG_ERR_UNSUPPORTED, "corrected stage needs FP32 1D2V dense whole-f states");
+    dgk::StageArgs<float> p;
+    fill_pack(c, &p, fin, fun, out, E, partials, c_un, c_in, c_dt);
+    p.reverse = reverse ? 1 : 0;
+    p.corr = corr;
+    p.corr_xm = corr_xm;
+    e = dgk::launch_stage(c->cfg.nv, c->L.n, false, &p, c->L.ntiles, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "corrected stage kernel launch");
+    return DG_OK;
+  }
   if (c->f64()) {
     dgk::StageArgs<double> p;
     fill_pack(c, &p, fin, fun, out, E, partials, c_un, c_in, c_dt);

@@ -60,7 +60,8 @@ dg_status hip_fail(dg_ctx* c, hipError_t e, const char* what);
 // out = c_un un + c_in fin + c_dt L(fin) with field E; density partials of out
 // into `partials` when non-NULL.
 dg_status stage(dg_ctx* c, const void* fin, const void* fun, void* out, const double* E, double* partials,
-                double c_un, double c_in, double c_dt, bool reverse = false);
+                double c_un, double c_in, double c_dt, bool reverse = false, const float* corr = nullptr,
+                const float* corr_xm = nullptr);
 // Density partials of f (FP64) into the workspace.
 dg_status density(dg_ctx* c, const void* f);
 // Velocity moments of f into the diagnostics ring (after a recording field solve).

@@ -31,6 +31,8 @@ struct StageArgs {
   const T* bg_u;          // background tables (state-row layout, storage precision) or nullptr:
   const T* bg_b;          //   1D2V G_u, G_b of L(f0) = -E G_u + G_b; 1D1V bg_u = G_v (Nv*n)
   const double* bg64;     // background f0 (FP64, dense [Nu*n][Nv*n] or [Nv*n]) for the moments, or nullptr
+  const float* corr;      // FP32 1D2V dense states: a correction added to L (state layout), or nullptr
+  const float* corr_xm;   //   and its x average per (u node, v node), subtracted, or nullptr
   double hu;              // du/2 (u-axis Jacobian inverse), nv = 2
   int Nx, Nu, Nv, nvchunks;
   int cpitch, lpitch;     // values per v chunk / per (x node, u node) row of the arrays

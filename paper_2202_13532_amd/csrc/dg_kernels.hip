@@ -315,6 +315,16 @@ template <typename T, int N>
 static hipError_t stage_t(int nv, const void* args, int ntiles, hipStream_t s) {
   const StageArgs<T>& a = *static_cast<const StageArgs<T>*>(args);
   const bool un = a.c_un != T(0);
+  if (a.corr) {
+    // the learned correction's stage: FP32 1D2V, no background
+    if constexpr (sizeof(T) == 4) {
+      if (nv != 2 || a.bg_u) return hipErrorInvalidValue;
+      if (un) hipLaunchKernelGGL((stage2v_kernel<T, N, true, false, true>), dim3(ntiles), dim3(kWave), 0, s, a);
+      else hipLaunchKernelGGL((stage2v_kernel<T, N, false, false, true>), dim3(ntiles), dim3(kWave), 0, s, a);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   if (a.bg_u) stage_bg<T, N, true>(nv, un, a, ntiles, s);
   else stage_bg<T, N, false>(nv, un, a, ntiles, s);
   return hipGetLastError();

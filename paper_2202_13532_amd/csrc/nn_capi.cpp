@@ -788,11 +788,9 @@ dg_status corrected_stage(dg_ctx* c, dg_nn* nn, const float* mean, const float* 
   if ((e = dgn::launch_scatter(sc, s)) != hipSuccess) return dgi::hip_fail(c, e, "scatter launch");
   if (fluct && (e = dgn::launch_xmean(corr, c->at<double>(L.off_wx), xm_c, nx, inner, s)) != hipSuccess)
     return dgi::hip_fail(c, e, "xmean launch");
-  NN_TRY(dgi::stage(c, fin, fun, out, E, nullptr, c_un, c_in, c_dt));
-  if ((e = dgn::launch_axpy(static_cast<float*>(out), corr, xm_c, static_cast<float>(c_dt), static_cast<size_t>(nx), inner, s)) !=
-      hipSuccess)
-    return dgi::hip_fail(c, e, "axpy launch");
-  NN_TRY(dgi::density(c, out));
+  // the stage adds c_dt (corr - xm_c) to its update and forms the density
+  // partials of the result itself
+  NN_TRY(dgi::stage(c, fin, fun, out, E, c->at<double>(L.off_part), c_un, c_in, c_dt, false, corr, xm_c));
   return dgi::field(c, E, nullptr, record);
 }
 

@@ -219,7 +219,9 @@ constexpr int lds_words_1v() { return (N + 1) * lds_row<N>(); }
 // BG: the state holds g = f - f0 for an x-uniform background f0(u, v)
 // (dg_set_background); the RHS then adds L(f0) = -E(x) G_u(u, v) + G_b(u, v),
 // two FP64-built tables in the state's row layout.
-template <typename T, int N, bool UN, bool BG = false>
+// CORR (FP32, dense rows): L + (corr - corr_xm) in place of L, the
+// correction read one row ahead like u^n (the learned correction's stage).
+template <typename T, int N, bool UN, bool BG = false, bool CORR = false>
 __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* lds, T* hbuf, double* dsum) {
   // every fused multiply-add is written out (fmadd): the rounding then does
   // not depend on the kernel this code is inlined into
@@ -394,6 +396,17 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
 #pragma unroll
     for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld(ru, vrow(0, iu), ju * rowb);
   }
+  // correction rows (one ahead) and its x average (the same for every x node)
+  T crr[CORR ? N : 1], cxm[CORR ? N : 1];
+  const auto rc = CORR ? xelem_rsrc(reinterpret_cast<const T*>(a.corr), xstride, ix, xbytes) : rf;
+  if constexpr (CORR) {
+#pragma unroll
+    for (int ju = 0; ju < N; ++ju) {
+      crr[ju] = B::ld(rc, vrow(0, iu), ju * rowb);
+      cxm[ju] = (a.corr_xm && act) ? static_cast<T>(a.corr_xm[(iu * N + ju) * static_cast<unsigned>(LP) + m0 + lane])
+                                   : T(0);
+    }
+  }
   // u-face values: without u^n (stage 1) the registers allow fetching all N
   // of them with the slab; with u^n they are fetched one row ahead
   constexpr int NUH = UN ? 1 : N;
@@ -419,6 +432,7 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
     for (int ju = 0; ju < N; ++ju) {
       T rhs = acc[ju] + lo[ju * ROW + 1 + lane];
       if constexpr (BG) rhs += fmadd(mE, bgu[ju], bgb[ju]);
+      if constexpr (CORR) rhs += crr[ju] - cxm[ju];
       // with u^n: f + c_un (u^n - f) = c_un u^n + (1 - c_un) f; a nearly
       // steady state then stays bit-identical instead of picking up the same
       // rounding every step (a mass drift in FP32)
@@ -431,6 +445,13 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
       const unsigned vj = vrow(jx + 1, iu);
 #pragma unroll
       for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld(ru, vj, ju * rowb);
+    }
+    if constexpr (CORR) {
+      if (jx + 1 < N) {
+        const unsigned vj = vrow(jx + 1, iu);
+#pragma unroll
+        for (int ju = 0; ju < N; ++ju) crr[ju] = B::ld(rc, vj, ju * rowb);
+      }
     }
     // density partial: (du/2) sum_ju w_ju v, reference weights as literals
     double sum = 0.0;
@@ -652,14 +673,14 @@ __device__ __forceinline__ void stage1v_tile(const StageArgs<T> a, int bid, T* l
 template <typename T, int N>
 constexpr int stage_min_waves() { return sizeof(T) == 8 && N >= 9 && N <= 11 ? 1 : 2; }
 
-template <typename T, int N, bool UN, bool BG>
+template <typename T, int N, bool UN, bool BG, bool CORR = false>
 __global__ void __launch_bounds__(kWave, (stage_min_waves<T, N>())) stage2v_kernel(StageArgs<T> a) {
   __shared__ T lds[lds_words_2v<N>()];
   __shared__ T hbuf[N * N];
   __shared__ double dsum[dens_words<T, N>()];
   // reversed order: the tiles the previous stage wrote last are read first
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  stage2v_tile<T, N, UN, BG>(a, a.reverse ? static_cast<int>(gridDim.x) - 1 - b : b, lds, hbuf, dsum);
+  stage2v_tile<T, N, UN, BG, CORR>(a, a.reverse ? static_cast<int>(gridDim.x) - 1 - b : b, lds, hbuf, dsum);
 }
 
 template <typename T, int N, bool UN, bool BG>

@@ -505,7 +505,10 @@ def dg_batch_set_choice(b, choice):
 
 
 class Batch:
-    """Many independent runs stepped by one persistent launch per RK stage."""
+    """Many independent runs (FP32) stepped together: per RK stage one launch
+    per kind (the 1D2V runs of one node count; all 1D1V runs), each a
+    persistent grid or one work-group per tile as the tuner chose, then one
+    batched field solve, replayed from a captured graph."""
 
     def __init__(self, configs, device="cuda"):
         import torch

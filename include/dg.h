@@ -267,7 +267,8 @@ dg_status dg_batch_destroy(dg_batch* b);
 
 /* Advance every run r by nsteps SSP-RK3 steps of its own dt[r] (host array)
  * on its state f[r] (host array of device pointers): per RK stage one
- * persistent launch per kind present, covering all runs of that kind,
+ * launch per kind present (persistent or one work-group per tile, as chosen
+ * by dg_batch_tune or dg_batch_set_choice), covering all runs of that kind,
  * then one batched field launch pair for all runs, replayed from a captured
  * HIP graph.  CFL and finiteness checks per run as
  * dg_rk_step.  host_diag: NULL or nruns*nsteps records, run-major

@@ -152,6 +152,25 @@ def test_fused_forward_matches_layerwise_and_oracle(sizes):
     net.close()
 
 
+def test_fused_form_rejected_for_wide_layers():
+    """A layer wider than 128 has no fused form: asking for it returns
+    DG_ERR_UNSUPPORTED and inference keeps the per-layer GEMMs (still against
+    the oracle)."""
+    rows, sizes = 300, [40, 200, 16]
+    rng = np.random.default_rng(4)
+    ps = _he_params(sizes, 6)
+    net = dg.Network(sizes, rows)
+    net.set_params(dg.Network.flatten(ps))
+    with pytest.raises(dg.DGError) as ex:
+        net.set_fused(True)
+    assert ex.value.status == dg.DG_ERR_UNSUPPORTED
+    Xd, Xv = _x_tensor(rng.standard_normal((rows, sizes[0])), net.ld)
+    y = net.forward(Xd).cpu().numpy().astype(np.float64)
+    y_ref, _ = mlp.forward(_round_weights(ps), Xv)
+    assert _rel_l2(y, y_ref) < 2e-2
+    net.close()
+
+
 def test_fused_forward_follows_parameter_updates():
     """The transposed weights of the fused kernel are refreshed after
     set_params and after AdamW steps: the fused and per-layer forms agree

@@ -23,7 +23,8 @@ The JSON line also carries
   sweep         -- the batched 64-run uneven sweep under the tuner's choice,
                    against its solo runs (--no-sweep skips it).
 --pattern-copy prints the copy references instead (streaming and tile-pattern
-copies of one state buffer next to the stage kernels); --nn-step times the
+copies of one state buffer next to the stage kernels, and the time of one
+empty dependent launch next to the field solve's); --nn-step times the
 learned correction's corrected coarse step (fused and per-layer network);
 --write-traffic summarises two rocprofv3 counter runs into the traffic file.
 """
@@ -462,13 +463,18 @@ def main():
         state_bytes = f.numel() * f.element_size()
         ms_lin = s.profile_copy(f, 0, 20)
         ms_pat = s.profile_copy(f, 1, 20)
+        ms_launch = s.profile_copy(f, 2, 200)
         rec = {"metric": "copy references (GB/s, read + write)", "workload": wl.name, "storage": wl.storage,
                "layout": layout, "state_bytes": state_bytes,
                "linear_copy": {"ms": ms_lin, "GBs": 2 * state_bytes / (ms_lin / 1e3) / 1e9},
                "tile_pattern_copy": {"ms": ms_pat, "GBs": 2 * state_bytes / (ms_pat / 1e3) / 1e9},
                "stage_kernels_GBs_algorithmic": [b / (t / 1e3) / 1e9 for b, t in
                                                  zip(bytes_per_launch, st_ms.mean(axis=0))],
-               "peak_GBs": HBM_PEAK_GBS}
+               "peak_GBs": HBM_PEAK_GBS,
+               # the field solve is two dependent launches per stage: its floor
+               "dependent_empty_launch_us": ms_launch * 1e3,
+               "field_pair_us": [float(x) * 1e3 for x in fld_ms.mean(axis=0)],
+               "step_ms": ms / args.steps, "stage_ms_sum": float(st_ms.mean(axis=0).sum())}
         print(json.dumps(rec), flush=True)
         s.close()
         return

@@ -212,7 +212,10 @@ dg_status dg_set_background(dg_ctx* ctx, const double* f0_host);
  * pattern 0: a plain streaming copy (16-byte accesses; the state's size
  * rounded down to 16 bytes); pattern 1 (1D2V): the stage kernel's own access
  * pattern -- its tiles, their order and store policy -- with no halos and no
- * arithmetic.  Each moves 2 * dg_state_elems() * sizeof(storage) bytes.    */
+ * arithmetic.  Each moves 2 * dg_state_elems() * sizeof(storage) bytes.
+ * pattern 2: an empty kernel (in and out untouched): the time of one launch
+ * that waits for the one before it on the stream, the floor under each of
+ * the step's kernels.                                                       */
 dg_status dg_profile_copy(dg_ctx* ctx, const void* in, void* out, int32_t pattern, int32_t reps, double* host_ms);
 
 /* Full diagnostics of state f (its own Poisson solve) into *host_out; waits.

@@ -747,9 +747,10 @@ dg_status dg_profile_copy(dg_ctx* ctx, const void* in, void* out, int32_t patter
   if (!in || !out || !host_ms || reps < 1) return fail(ctx, DG_ERR_INVALID, "dg_profile_copy: bad argument");
   if (in == out) return fail(ctx, DG_ERR_INVALID, "dg_profile_copy: in and out must not overlap");
   if (pattern == 1 && ctx->cfg.nv != 2) return fail(ctx, DG_ERR_UNSUPPORTED, "dg_profile_copy: the tile pattern is 1D2V");
-  if (pattern != 0 && pattern != 1) return fail(ctx, DG_ERR_INVALID, "dg_profile_copy: pattern must be 0 or 1");
+  if (pattern < 0 || pattern > 2) return fail(ctx, DG_ERR_INVALID, "dg_profile_copy: pattern must be 0, 1 or 2");
   const Layout& L = ctx->L;
   auto launch = [&]() -> hipError_t {
+    if (pattern == 2) return dgk::launch_empty(ctx->stream);
     if (pattern == 0) return dgk::launch_linear_copy(in, out, L.selems * L.esize / 16 * 16, ctx->stream);
     if (ctx->f64()) {
       dgk::StageArgs<double> p;

@@ -187,8 +187,13 @@ __global__ void reset_counter_kernel(int* c) { *c = 0; }
 //   pattern_copy_kernel: the 1D2V stage kernel's access pattern without its
 //     halos or arithmetic: one wave per tile (same tiles, XCD remap and
 //     buffer resources), the tile's n x n rows of one v chunk loaded, then
-//     stored (unused slots of padded rows written as zeros).
+//     stored (unused slots of padded rows written as zeros);
+//   empty_kernel: no work; a chain of them on one stream gives the time of
+//     one dependent launch (dispatch, the kernel-boundary cache operations,
+//     completion), the floor under every kernel of the step.
 // -------------------------------------------------------------------------
+__global__ void __launch_bounds__(kWave) empty_kernel() {}
+
 __global__ void __launch_bounds__(256) linear_copy_kernel(const float4* __restrict__ in, float4* __restrict__ out,
                                                           size_t n16) {
   for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n16;
@@ -394,6 +399,11 @@ hipError_t launch_moments_reduce(const double* mom, int ntiles, double* ring, co
   return hipGetLastError();
 }
 
+
+hipError_t launch_empty(hipStream_t s) {
+  hipLaunchKernelGGL(empty_kernel, dim3(1), dim3(kWave), 0, s);
+  return hipGetLastError();
+}
 
 hipError_t launch_linear_copy(const void* in, void* out, size_t bytes, hipStream_t s) {
   const size_t n16 = bytes / 16;

@@ -379,7 +379,8 @@ class Solver:
         return dg_rk_step(self.ctx, f, dt, nsteps, diag)
 
     def profile_copy(self, f, pattern, reps=20):
-        """Mean ms of a copy of state f: pattern 0 streaming, 1 the stage kernel's tile pattern."""
+        """Mean ms of a copy of state f: pattern 0 streaming, 1 the stage kernel's tile pattern;
+        pattern 2 times an empty dependent launch instead (f untouched)."""
         self._check_state(f)
         out = self.empty_state()
         return dg_profile_copy(self.ctx, f, out, pattern, reps)

@@ -187,3 +187,26 @@ def test_layout_calls_reject_bad_arguments():
     with pytest.raises(dg.DGError):
         p.step(f, 1e-3, 1)                              # a dense array is not a padded state
     p.close()
+
+
+def test_copy_references_copy_the_state_and_time_a_launch():
+    """The bandwidth references: the streaming copy and the tile-pattern copy
+    reproduce a padded 1D2V state exactly (pad slots are zero in a packed
+    state); the empty-launch reference leaves its buffers alone."""
+    s = dg.Solver(2, 5, [3, 4, 13], [0.0, -6.0, -6.0], [5.0, 6.0, 6.0], 0.5, layout="vpad")
+    f = s.pack(torch.rand(s.dense_shape, dtype=torch.float32, device="cuda") + 0.1)
+    for pattern in (0, 1):
+        out = s.empty_state()
+        out.fill_(-1.0)
+        ms = dg.dg_profile_copy(s.ctx, f, out, pattern, 2)
+        assert ms > 0
+        nb = f.numel() * f.element_size() // 16 * 16 // f.element_size()
+        assert torch.equal(out.flatten()[:nb], f.flatten()[:nb]), pattern
+    out = s.empty_state()
+    out.fill_(-1.0)
+    before = f.clone()
+    assert dg.dg_profile_copy(s.ctx, f, out, 2, 5) > 0
+    assert torch.equal(f, before) and bool((out == -1.0).all())
+    with pytest.raises(dg.DGError):
+        dg.dg_profile_copy(s.ctx, f, out, 3, 1)
+    s.close()

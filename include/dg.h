@@ -347,7 +347,8 @@ dg_status dg_nn_get_params(dg_nn* nn, float* host_params);
 dg_status dg_nn_forward(dg_nn* nn, const uint16_t* X, int32_t rows, float* Y);
 /* Inference form: on = 1 (default) the fused launch where the shape allows
  * it, 0 one GEMM launch per layer (the form training uses).  Returns
- * DG_ERR_UNSUPPORTED for on = 1 when the shape has no fused form.          */
+ * DG_ERR_UNSUPPORTED for on = 1 when the shape has no fused form, and then
+ * changes nothing.                                                          */
 dg_status dg_nn_set_fused(dg_nn* nn, int32_t on);
 /* Forward + backward of the MSE loss mean((Y - T)^2) for targets T (device,
  * rows x out FP32); *loss receives the loss (host, waits); host_grads (may be

@@ -460,6 +460,7 @@ dg_status dg_nn_forward(dg_nn* nn, const uint16_t* X, int32_t rows, float* Y) {
 dg_status dg_nn_set_fused(dg_nn* nn, int32_t on) {
   if (!nn) return DG_ERR_INVALID;
   if (on != 0 && on != 1) return nfail(nn, DG_ERR_INVALID, "dg_nn_set_fused: on must be 0 or 1");
+  if (on != 0 && !nn->N.fusable) return nfail(nn, DG_ERR_UNSUPPORTED, "this network's shape has no fused form");
   if ((on != 0) != nn->fused) {
     nn->fused = on != 0;
     // a cached corrected step holds the other form
@@ -469,7 +470,7 @@ dg_status dg_nn_set_fused(dg_nn* nn, int32_t on) {
       nn->gexec = nullptr;
     }
   }
-  return nn->N.fusable || on == 0 ? DG_OK : nfail(nn, DG_ERR_UNSUPPORTED, "this network's shape has no fused form");
+  return DG_OK;
 }
 
 dg_status dg_nn_loss_grad(dg_nn* nn, const uint16_t* X, const float* T, int32_t rows, double* loss, float* host_grads) {

@@ -402,7 +402,7 @@ def main():
     if args.write_traffic:
         return write_traffic(*args.write_traffic, workload=args.workload)
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the x-slab sharding is a design note); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

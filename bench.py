@@ -464,10 +464,14 @@ def main():
         ms_lin = s.profile_copy(f, 0, 20)
         ms_pat = s.profile_copy(f, 1, 20)
         ms_launch = s.profile_copy(f, 2, 200)
+        ms_pat_res = s.profile_copy(f, 3, 20)
         rec = {"metric": "copy references (GB/s, read + write)", "workload": wl.name, "storage": wl.storage,
                "layout": layout, "state_bytes": state_bytes,
                "linear_copy": {"ms": ms_lin, "GBs": 2 * state_bytes / (ms_lin / 1e3) / 1e9},
                "tile_pattern_copy": {"ms": ms_pat, "GBs": 2 * state_bytes / (ms_pat / 1e3) / 1e9},
+               # the same copy with no more work-groups resident per CU than the stage-1 kernel
+               "tile_pattern_copy_stage_residency": {"ms": ms_pat_res,
+                                                     "GBs": 2 * state_bytes / (ms_pat_res / 1e3) / 1e9},
                "stage_kernels_GBs_algorithmic": [b / (t / 1e3) / 1e9 for b, t in
                                                  zip(bytes_per_launch, st_ms.mean(axis=0))],
                "peak_GBs": HBM_PEAK_GBS,

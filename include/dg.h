@@ -215,7 +215,9 @@ dg_status dg_set_background(dg_ctx* ctx, const double* f0_host);
  * arithmetic.  Each moves 2 * dg_state_elems() * sizeof(storage) bytes.
  * pattern 2: an empty kernel (in and out untouched): the time of one launch
  * that waits for the one before it on the stream, the floor under each of
- * the step's kernels.                                                       */
+ * the step's kernels.  pattern 3 (1D2V): pattern 1 with no more work-groups
+ * resident per CU than the stage-1 kernel of this shape (unused LDS per
+ * work-group); DG_ERR_DEVICE where that would take more than 64 KiB of LDS. */
 dg_status dg_profile_copy(dg_ctx* ctx, const void* in, void* out, int32_t pattern, int32_t reps, double* host_ms);
 
 /* Full diagnostics of state f (its own Poisson solve) into *host_out; waits.

@@ -746,8 +746,9 @@ dg_status dg_profile_copy(dg_ctx* ctx, const void* in, void* out, int32_t patter
   if (!ctx) return DG_ERR_INVALID;
   if (!in || !out || !host_ms || reps < 1) return fail(ctx, DG_ERR_INVALID, "dg_profile_copy: bad argument");
   if (in == out) return fail(ctx, DG_ERR_INVALID, "dg_profile_copy: in and out must not overlap");
-  if (pattern == 1 && ctx->cfg.nv != 2) return fail(ctx, DG_ERR_UNSUPPORTED, "dg_profile_copy: the tile pattern is 1D2V");
-  if (pattern < 0 || pattern > 2) return fail(ctx, DG_ERR_INVALID, "dg_profile_copy: pattern must be 0, 1 or 2");
+  if (pattern < 0 || pattern > 3) return fail(ctx, DG_ERR_INVALID, "dg_profile_copy: pattern must be 0..3");
+  if ((pattern == 1 || pattern == 3) && ctx->cfg.nv != 2)
+    return fail(ctx, DG_ERR_UNSUPPORTED, "dg_profile_copy: the tile pattern is 1D2V");
   const Layout& L = ctx->L;
   auto launch = [&]() -> hipError_t {
     if (pattern == 2) return dgk::launch_empty(ctx->stream);
@@ -755,11 +756,11 @@ dg_status dg_profile_copy(dg_ctx* ctx, const void* in, void* out, int32_t patter
     if (ctx->f64()) {
       dgk::StageArgs<double> p;
       fill_pack(ctx, &p, in, in, out, nullptr, nullptr, 0, 0, 0);
-      return dgk::launch_pattern_copy(2, L.n, true, &p, L.ntiles, ctx->stream);
+      return dgk::launch_pattern_copy(2, L.n, true, &p, L.ntiles, pattern == 3, ctx->stream);
     }
     dgk::StageArgs<float> p;
     fill_pack(ctx, &p, in, in, out, nullptr, nullptr, 0, 0, 0);
-    return dgk::launch_pattern_copy(2, L.n, false, &p, L.ntiles, ctx->stream);
+    return dgk::launch_pattern_copy(2, L.n, false, &p, L.ntiles, pattern == 3, ctx->stream);
   };
   DG_TRY(enter(ctx));
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -76,7 +76,8 @@ hipError_t launch_reset_counter(int* counter, hipStream_t s);
 // and the 1D2V stage kernel's tile access pattern without halos or arithmetic
 hipError_t launch_linear_copy(const void* in, void* out, size_t bytes, hipStream_t s);
 hipError_t launch_empty(hipStream_t s);
-hipError_t launch_pattern_copy(int nv, int n, bool f64, const void* args, int ntiles, hipStream_t s);
+hipError_t launch_pattern_copy(int nv, int n, bool f64, const void* args, int ntiles, bool stage_residency,
+                               hipStream_t s);
 // c_p (2*pmax doubles) = T (node-major [nodes][pmax] complex) applied to g (nodes)
 hipError_t launch_fourier(const double* T, const double* g, int nodes, int pmax, double* out, hipStream_t s);
 // out = M in along the x rows: M R x R, states R x C, storage precision

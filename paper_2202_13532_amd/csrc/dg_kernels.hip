@@ -189,12 +189,16 @@ __global__ void reset_counter_kernel(int* c) { *c = 0; }
 //   pattern_copy_kernel: the 1D2V stage kernel's access pattern without its
 //     halos or arithmetic: one wave per tile (same tiles, XCD remap and
 //     buffer resources), the tile's n x n rows of one v chunk loaded, then
-//     stored (unused slots of padded rows written as zeros);
+//     stored (unused slots of padded rows written as zeros); optionally
+//     held to the stage-1 kernel's residency per CU;
 //   empty_kernel: no work; a chain of them on one stream gives the time of
 //     one dependent launch (dispatch, the kernel-boundary cache operations,
 //     completion), the floor under every kernel of the step.
 // -------------------------------------------------------------------------
 __global__ void __launch_bounds__(kWave) empty_kernel() {}
+
+constexpr int kLdsPerCu = 160 * 1024;   // LDS of one gfx950 CU
+constexpr int kLdsGranule = 512;        // LDS allocation granularity (bytes)
 
 __global__ void __launch_bounds__(256) linear_copy_kernel(const float4* __restrict__ in, float4* __restrict__ out,
                                                           size_t n16) {
@@ -419,15 +423,28 @@ hipError_t launch_linear_copy(const void* in, void* out, size_t bytes, hipStream
 }
 
 template <typename T, int N>
-static hipError_t pattern_copy_t(int nv, const void* args, int ntiles, hipStream_t s) {
+static hipError_t pattern_copy_t(int nv, const void* args, int ntiles, bool stage_residency, hipStream_t s) {
   if (nv != 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((pattern_copy_kernel<T, N>), dim3(ntiles), dim3(kWave), 0, s, *static_cast<const StageArgs<T>*>(args));
+  size_t lds = 0;
+  if (stage_residency) {
+    // unused LDS per work-group, sized so that no more of them fit on a CU
+    // than work-groups of the stage-1 kernel of this shape (the copy alone
+    // would keep more waves resident)
+    int per_cu = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, stage2v_kernel<T, N, false, false, false>, kWave, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 3) return hipErrorInvalidValue;   // would need more than 64 KiB per work-group
+    lds = static_cast<size_t>(kLdsPerCu / per_cu) / kLdsGranule * kLdsGranule;
+  }
+  hipLaunchKernelGGL((pattern_copy_kernel<T, N>), dim3(ntiles), dim3(kWave), lds, s, *static_cast<const StageArgs<T>*>(args));
   return hipGetLastError();
 }
 
-hipError_t launch_pattern_copy(int nv, int n, bool f64, const void* args, int ntiles, hipStream_t s) {
-  if (f64) { DG_DISPATCH_N(pattern_copy_t, double, nv, args, ntiles, s) }
-  DG_DISPATCH_N(pattern_copy_t, float, nv, args, ntiles, s)
+hipError_t launch_pattern_copy(int nv, int n, bool f64, const void* args, int ntiles, bool stage_residency,
+                               hipStream_t s) {
+  if (f64) { DG_DISPATCH_N(pattern_copy_t, double, nv, args, ntiles, stage_residency, s) }
+  DG_DISPATCH_N(pattern_copy_t, float, nv, args, ntiles, stage_residency, s)
 }
 
 hipError_t launch_fourier(const double* T, const double* g, int nodes, int pmax, double* out, hipStream_t s) {

@@ -380,7 +380,8 @@ class Solver:
 
     def profile_copy(self, f, pattern, reps=20):
         """Mean ms of a copy of state f: pattern 0 streaming, 1 the stage kernel's tile pattern;
-        pattern 2 times an empty dependent launch instead (f untouched)."""
+        pattern 2 times an empty dependent launch instead (f untouched); pattern 3 is
+        pattern 1 held to the stage-1 kernel's residency per CU."""
         self._check_state(f)
         out = self.empty_state()
         return dg_profile_copy(self.ctx, f, out, pattern, reps)

@@ -191,11 +191,12 @@ def test_layout_calls_reject_bad_arguments():
 
 def test_copy_references_copy_the_state_and_time_a_launch():
     """The bandwidth references: the streaming copy and the tile-pattern copy
-    reproduce a padded 1D2V state exactly (pad slots are zero in a packed
-    state); the empty-launch reference leaves its buffers alone."""
+    (also held to the stage kernel's residency) reproduce a padded 1D2V
+    state exactly (pad slots are zero in a packed state); the empty-launch
+    reference leaves its buffers alone."""
     s = dg.Solver(2, 5, [3, 4, 13], [0.0, -6.0, -6.0], [5.0, 6.0, 6.0], 0.5, layout="vpad")
     f = s.pack(torch.rand(s.dense_shape, dtype=torch.float32, device="cuda") + 0.1)
-    for pattern in (0, 1):
+    for pattern in (0, 1, 3):
         out = s.empty_state()
         out.fill_(-1.0)
         ms = dg.dg_profile_copy(s.ctx, f, out, pattern, 2)
@@ -208,5 +209,5 @@ def test_copy_references_copy_the_state_and_time_a_launch():
     assert dg.dg_profile_copy(s.ctx, f, out, 2, 5) > 0
     assert torch.equal(f, before) and bool((out == -1.0).all())
     with pytest.raises(dg.DGError):
-        dg.dg_profile_copy(s.ctx, f, out, 3, 1)
+        dg.dg_profile_copy(s.ctx, f, out, 4, 1)
     s.close()

@@ -150,6 +150,9 @@ template <> struct Buf<float> {
   __device__ static float ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
   }
+  __device__ static float ld_nt(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, kCpolNT));
+  }
   __device__ static void st(float v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, vo, so, 0);
   }
@@ -160,6 +163,9 @@ template <> struct Buf<float> {
 template <> struct Buf<double> {
   __device__ static double ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+  }
+  __device__ static double ld_nt(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, kCpolNT));
   }
   __device__ static void st(double v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
     typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
@@ -390,11 +396,16 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
       bgb[ju] = B::ld(rgb, vb, ju * rowb);
     }
   }
-  // rows of u^n and of the u face are fetched one row ahead of their use
+  // rows of u^n and of the u face are fetched one row ahead of their use.
+  // u^n rows are read by this tile only, so they are loaded with the
+  // non-temporal hint (measured: 0.759 -> 0.748 ms per step on the 107.5 M
+  // DOF workload, results bitwise unchanged); the slab rows keep the default
+  // policy, since neighbouring tiles read their faces and v edge values
+  // (the hint there cost 1.3 %).
   T unr[N];
   if (UN) {
 #pragma unroll
-    for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld(ru, vrow(0, iu), ju * rowb);
+    for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld_nt(ru, vrow(0, iu), ju * rowb);
   }
   // correction rows (one ahead) and its x average (the same for every x node)
   T crr[CORR ? N : 1], cxm[CORR ? N : 1];
@@ -444,7 +455,7 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
     if (UN && jx + 1 < N) {
       const unsigned vj = vrow(jx + 1, iu);
 #pragma unroll
-      for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld(ru, vj, ju * rowb);
+      for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld_nt(ru, vj, ju * rowb);
     }
     if constexpr (CORR) {
       if (jx + 1 < N) {

@@ -345,8 +345,8 @@ def write_traffic(fetch_dir, write_dir, workload="maxwell_1d2v_n9"):
     F, W = per_kernel(fetch_dir), per_kernel(write_dir)
     n = wl.n
     # the plain stage kernels (template arguments T, n, UN, BG[, CORR])
-    k1 = r"stage2v_kernel<float, %d, false, false(, false)?>" % n
-    k23 = r"stage2v_kernel<float, %d, true, false(, false)?>" % n
+    k1 = r"stage2v_kernel<float, %d, false, false(, false)*>" % n
+    k23 = r"stage2v_kernel<float, %d, true, false(, false)?(, (true|false))?>" % n
     s1f, s23f = find(F, k1), find(F, k23)
     s1w, s23w = find(W, k1), find(W, k23)
     # the calibration copies: the large copyBuffer dispatches

@@ -70,15 +70,16 @@ __device__ __forceinline__ void batched_walk(const StageArgs<float>* __restrict_
   }
 }
 
-template <bool UN, int N>
+template <bool UN, int N, bool UNNT = false>
 __global__ void __launch_bounds__(kWave, 2) stage_batched_kernel(const StageArgs<float>* __restrict__ runs,
                                                                   const int2* __restrict__ items,
                                                                   const int* __restrict__ xcd_begin) {
   __shared__ float lds[lds_words_2v<N>()];
   __shared__ float hbuf[N * N];
   __shared__ double dsum[dens_words<float, N>()];
-  batched_walk(runs, items, xcd_begin,
-               [&](const StageArgs<float>& a, int tile) { stage2v_tile<float, N, UN>(a, tile, lds, hbuf, dsum); });
+  batched_walk(runs, items, xcd_begin, [&](const StageArgs<float>& a, int tile) {
+    stage2v_tile<float, N, UN, false, false, UNNT>(a, tile, lds, hbuf, dsum);
+  });
 }
 
 template <bool UN>
@@ -101,9 +102,11 @@ __global__ void __launch_bounds__(kFieldB) fieldB_batched_kernel(const FieldArgs
 
 
 template <int N>
-static hipError_t stage_batched_t(bool un, const StageArgs<float>* runs, const int2* items, const int* xcd_begin, int grid,
-                                  hipStream_t s) {
-  if (un) hipLaunchKernelGGL((stage_batched_kernel<true, N>), dim3(grid), dim3(kWave), 0, s, runs, items, xcd_begin);
+static hipError_t stage_batched_t(bool un, bool un_nt, const StageArgs<float>* runs, const int2* items,
+                                  const int* xcd_begin, int grid, hipStream_t s) {
+  if (un && un_nt)
+    hipLaunchKernelGGL((stage_batched_kernel<true, N, true>), dim3(grid), dim3(kWave), 0, s, runs, items, xcd_begin);
+  else if (un) hipLaunchKernelGGL((stage_batched_kernel<true, N>), dim3(grid), dim3(kWave), 0, s, runs, items, xcd_begin);
   else hipLaunchKernelGGL((stage_batched_kernel<false, N>), dim3(grid), dim3(kWave), 0, s, runs, items, xcd_begin);
   return hipGetLastError();
 }
@@ -114,7 +117,7 @@ static int occ_of_kernel(K kernel) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kWave, 0) == hipSuccess ? nb : 0;
 }
 
-hipError_t launch_stage_batched(bool un, int n, int nv, const StageArgs<float>* runs, const int2* items,
+hipError_t launch_stage_batched(bool un, bool un_nt, int n, int nv, const StageArgs<float>* runs, const int2* items,
                                 const int* xcd_begin, int grid, hipStream_t s) {
   if (grid < 1) return hipErrorInvalidValue;
   if (nv == 1) {
@@ -124,7 +127,7 @@ hipError_t launch_stage_batched(bool un, int n, int nv, const StageArgs<float>* 
   }
   switch (n) {
 #define DG_BATCH_CASE(NN) \
-  case NN: return stage_batched_t<NN>(un, runs, items, xcd_begin, grid, s);
+  case NN: return stage_batched_t<NN>(un, un_nt, runs, items, xcd_begin, grid, s);
     DG_BATCH_CASE(2) DG_BATCH_CASE(3) DG_BATCH_CASE(4) DG_BATCH_CASE(5)
     DG_BATCH_CASE(6) DG_BATCH_CASE(7) DG_BATCH_CASE(8) DG_BATCH_CASE(9)
     DG_BATCH_CASE(10) DG_BATCH_CASE(11) DG_BATCH_CASE(12)

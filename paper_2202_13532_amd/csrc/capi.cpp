@@ -1001,6 +1001,7 @@ void tune_cache_put(const std::string& arch, int n, int nv, int wm) {
 
 struct dg_batch {
   int nruns = 0;
+  bool nt = false;   // the runs' buffers exceed the last-level cache: non-temporal stage stores and u^n loads
   std::vector<dg_ctx*> runs;
   std::vector<size_t> run_off;
   hipStream_t user = nullptr, stream = nullptr;
@@ -1140,7 +1141,8 @@ dg_status upload_args(dg_batch* b, void* const* f, const double* dt) {
   // the batch's runs share the cache: the store policy follows their total
   size_t total = 0;
   for (int r = 0; r < b->nruns; ++r) total += 3 * b->runs[r]->L.selems * b->runs[r]->L.esize;
-  for (auto& a : args) a.nt_store = total > kLastLevelCache ? 1 : 0;
+  b->nt = total > kLastLevelCache;
+  for (auto& a : args) a.nt_store = b->nt ? 1 : 0;
   DGB_HIP(b, hipMemcpyAsync(b->d_args, args.data(), args.size() * sizeof(args[0]), hipMemcpyHostToDevice, b->stream));
   DGB_HIP(b, hipMemcpyAsync(b->d_fa, fa.data(), fa.size() * sizeof(fa[0]), hipMemcpyHostToDevice, b->stream));
   DGB_HIP(b, hipStreamSynchronize(b->stream));
@@ -1152,7 +1154,7 @@ dg_status enqueue_batch_step(dg_batch* b, bool diag) {
   for (int k = 0; k < 3; ++k) {
     for (size_t q = 0; q < nk; ++q) {
       const auto& g = b->groups[q];
-      DGB_HIP(b, dgk::launch_stage_batched(k > 0, g.n, g.nv, b->d_args + k * b->nruns, b->d_items + g.begin,
+      DGB_HIP(b, dgk::launch_stage_batched(k > 0, b->nt, g.n, g.nv, b->d_args + k * b->nruns, b->d_items + g.begin,
                                            b->d_xcd + 9 * q, g.grid, b->stream));
     }
     DGB_HIP(b, dgk::launch_field_batched(b->d_fa + k * b->nruns, b->d_xitems, b->nxitems, b->nruns, b->max_pmax, b->stream));

@@ -91,8 +91,9 @@ hipError_t launch_repack(bool pack, bool f64, const void* in, void* out, size_t 
 // StageArgs<float> per run of the batch, `items` (device) the kind's (run,
 // tile) work list, `xcd_begin` (device, 9 entries, relative to `items`) its
 // split over the 8 XCDs.  nv = 2: the 1D2V runs of n nodes; nv = 1: the 1D1V
-// runs of any n (StageArgs::n1v; n ignored).
-hipError_t launch_stage_batched(bool un, int n, int nv, const StageArgs<float>* runs, const int2* items,
+// runs of any n (StageArgs::n1v; n ignored).  un_nt: the 1D2V u^n loads take
+// the non-temporal hint (the runs' buffers exceed the last-level cache).
+hipError_t launch_stage_batched(bool un, bool un_nt, int n, int nv, const StageArgs<float>* runs, const int2* items,
                                 const int* xcd_begin, int grid, hipStream_t s);
 // Batched field solve: `fa` (device) one FieldArgs per run, `xitems` (device)
 // the (run, x element) list.

@@ -314,7 +314,9 @@ __global__ void __launch_bounds__(256) xfilter_kernel(const T* __restrict__ in, 
 template <typename T, int N, bool BG>
 static void stage_bg(int nv, bool un, const StageArgs<T>& a, int ntiles, hipStream_t s) {
   if (nv == 2) {
-    if (un) hipLaunchKernelGGL((stage2v_kernel<T, N, true, BG>), dim3(ntiles), dim3(kWave), 0, s, a);
+    // u^n loads take the non-temporal hint together with the stores
+    if (un && a.nt_store) hipLaunchKernelGGL((stage2v_kernel<T, N, true, BG, false, true>), dim3(ntiles), dim3(kWave), 0, s, a);
+    else if (un) hipLaunchKernelGGL((stage2v_kernel<T, N, true, BG>), dim3(ntiles), dim3(kWave), 0, s, a);
     else hipLaunchKernelGGL((stage2v_kernel<T, N, false, BG>), dim3(ntiles), dim3(kWave), 0, s, a);
   } else {
     if (un) hipLaunchKernelGGL((stage1v_kernel<T, N, true, BG>), dim3(ntiles), dim3(kWave), 0, s, a);
@@ -330,7 +332,8 @@ static hipError_t stage_t(int nv, const void* args, int ntiles, hipStream_t s) {
     // the learned correction's stage: FP32 1D2V, no background
     if constexpr (sizeof(T) == 4) {
       if (nv != 2 || a.bg_u) return hipErrorInvalidValue;
-      if (un) hipLaunchKernelGGL((stage2v_kernel<T, N, true, false, true>), dim3(ntiles), dim3(kWave), 0, s, a);
+      if (un && a.nt_store) hipLaunchKernelGGL((stage2v_kernel<T, N, true, false, true, true>), dim3(ntiles), dim3(kWave), 0, s, a);
+      else if (un) hipLaunchKernelGGL((stage2v_kernel<T, N, true, false, true>), dim3(ntiles), dim3(kWave), 0, s, a);
       else hipLaunchKernelGGL((stage2v_kernel<T, N, false, false, true>), dim3(ntiles), dim3(kWave), 0, s, a);
       return hipGetLastError();
     }

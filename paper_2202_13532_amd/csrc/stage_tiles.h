@@ -227,7 +227,7 @@ constexpr int lds_words_1v() { return (N + 1) * lds_row<N>(); }
 // two FP64-built tables in the state's row layout.
 // CORR (FP32, dense rows): L + (corr - corr_xm) in place of L, the
 // correction read one row ahead like u^n (the learned correction's stage).
-template <typename T, int N, bool UN, bool BG = false, bool CORR = false>
+template <typename T, int N, bool UN, bool BG = false, bool CORR = false, bool UNNT = false>
 __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* lds, T* hbuf, double* dsum) {
   // every fused multiply-add is written out (fmadd): the rounding then does
   // not depend on the kernel this code is inlined into
@@ -397,15 +397,20 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
     }
   }
   // rows of u^n and of the u face are fetched one row ahead of their use.
-  // u^n rows are read by this tile only, so they are loaded with the
-  // non-temporal hint (measured: 0.759 -> 0.748 ms per step on the 107.5 M
-  // DOF workload, results bitwise unchanged); the slab rows keep the default
-  // policy, since neighbouring tiles read their faces and v edge values
-  // (the hint there cost 1.3 %).
+  // u^n rows are read by this tile only; UNNT (the launchers set it where
+  // the stage outputs take the non-temporal hint, i.e. buffers larger than
+  // the last-level cache) loads them with that hint too.  The slab rows keep
+  // the default policy, since neighbouring tiles read their faces and v
+  // edge values.  The hint is an immediate of the load instruction, so the
+  // two policies are two kernel instances, not a branch.
+  auto ld_un = [&](unsigned vo, unsigned so) -> T {
+    if constexpr (UNNT) return B::ld_nt(ru, vo, so);
+    else return B::ld(ru, vo, so);
+  };
   T unr[N];
   if (UN) {
 #pragma unroll
-    for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld_nt(ru, vrow(0, iu), ju * rowb);
+    for (int ju = 0; ju < N; ++ju) unr[ju] = ld_un(vrow(0, iu), ju * rowb);
   }
   // correction rows (one ahead) and its x average (the same for every x node)
   T crr[CORR ? N : 1], cxm[CORR ? N : 1];
@@ -455,7 +460,7 @@ __device__ __forceinline__ void stage2v_tile(const StageArgs<T> a, int bid, T* l
     if (UN && jx + 1 < N) {
       const unsigned vj = vrow(jx + 1, iu);
 #pragma unroll
-      for (int ju = 0; ju < N; ++ju) unr[ju] = B::ld_nt(ru, vj, ju * rowb);
+      for (int ju = 0; ju < N; ++ju) unr[ju] = ld_un(vj, ju * rowb);
     }
     if constexpr (CORR) {
       if (jx + 1 < N) {
@@ -684,14 +689,14 @@ __device__ __forceinline__ void stage1v_tile(const StageArgs<T> a, int bid, T* l
 template <typename T, int N>
 constexpr int stage_min_waves() { return sizeof(T) == 8 && N >= 9 && N <= 11 ? 1 : 2; }
 
-template <typename T, int N, bool UN, bool BG, bool CORR = false>
+template <typename T, int N, bool UN, bool BG, bool CORR = false, bool UNNT = false>
 __global__ void __launch_bounds__(kWave, (stage_min_waves<T, N>())) stage2v_kernel(StageArgs<T> a) {
   __shared__ T lds[lds_words_2v<N>()];
   __shared__ T hbuf[N * N];
   __shared__ double dsum[dens_words<T, N>()];
   // reversed order: the tiles the previous stage wrote last are read first
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  stage2v_tile<T, N, UN, BG, CORR>(a, a.reverse ? static_cast<int>(gridDim.x) - 1 - b : b, lds, hbuf, dsum);
+  stage2v_tile<T, N, UN, BG, CORR, UNNT>(a, a.reverse ? static_cast<int>(gridDim.x) - 1 - b : b, lds, hbuf, dsum);
 }
 
 template <typename T, int N, bool UN, bool BG>

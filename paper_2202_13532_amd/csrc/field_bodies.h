@@ -12,7 +12,8 @@ namespace dgk {
 // Field solve (FP64), two launches per stage (a kernel boundary orders the
 // hand-over; a device-scope fence would write back and invalidate L2).
 //   fieldA: block ix (256 threads) reduces the density partials of its x
-//           element in a fixed order and forms its Fourier sums
+//           element in a fixed order (each wave whole rows) and forms its
+//           Fourier sums
 //           sum_j T_p^{mj} (n_mj - 1)  (eq. spectral_transform) and its mass.
 //   fieldB: one block sums those in element order, synthesises E at every x
 //           node, E_mj = sum_{p=1..pmax} 2 Re((i / k_p) c_p e^{i k_p x_mj})
@@ -26,8 +27,10 @@ constexpr int kFieldB = 1024;
 
 constexpr int kFieldA = 256;
 
-// fieldA variants: LOADS partials per thread and pass (one pass covers
-// LOADS * 256 values, all loads of a pass in flight together); TPRE: fetch
+// fieldA variants: LOADS partials per lane, row and pass (one pass covers
+// LOADS * 64 values of each of the wave's rows, all loads of a pass in
+// flight together; the per-lane sums add the values in index order whatever
+// LOADS is, so both forms give the same bits); TPRE: fetch
 // the connection-tensor entries of the thread's first mode in the same
 // round trip as the partials.  The single-run solve (one block per x
 // element, never more than a few hundred blocks) takes the lowest-latency
@@ -41,7 +44,6 @@ __device__ __forceinline__ void fieldA_body(const FieldArgs& a, int ix) {
   #pragma clang fp contract(off)
   __shared__ double dens[kMaxN];
   __shared__ double wxs[kMaxN];
-  __shared__ double red[kFieldA / kWave][kMaxN];
   const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave, n = a.n;
   // Reads that do not depend on the density go out with the partials, in
   // one memory round trip: the connection-tensor entries of this thread's
@@ -57,50 +59,44 @@ __device__ __forceinline__ void fieldA_body(const FieldArgs& a, int ix) {
       }
   }
   const double wxj = tid < n ? a.wx[ix * n + tid] : 0.0;
-  // The element's partials are n rows of ntiles values, contiguous: thread
-  // tid takes values tid, tid + 256, ... in passes of kLoadsA loads, each
-  // added to the sum of its row; then wave sums, and the waves' results
-  // added in order.
-  double s[kMaxN];
-#pragma unroll
-  for (int j = 0; j < kMaxN; ++j) s[j] = 0.0;
+  // The element's partials are n rows of ntiles values, contiguous: wave w
+  // sums rows w, w + 4, w + 8 (lane-strided, every load of a pass in flight
+  // together), then its lanes in a fixed exchange pattern.
+  constexpr int kWaves = kFieldA / kWave;
+  constexpr int RW = (kMaxN + kWaves - 1) / kWaves;
   const double* base = a.partials + static_cast<size_t>(ix * n) * a.ntiles;
-  const int total = n * a.ntiles;
-  const float rnt = 1.0f / static_cast<float>(a.ntiles);
-  for (int q0 = 0; q0 < total; q0 += kFieldA * LOADS) {
-    double v[LOADS];
+  const int nt = a.ntiles;
+  double s[RW];
 #pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
-      const int idx = q0 + q * kFieldA + tid;
-      v[q] = idx < total ? base[idx] : 0.0;
+  for (int r = 0; r < RW; ++r) s[r] = 0.0;
+  for (int q0 = 0; q0 < nt; q0 += kWave * LOADS) {
+    double v[RW][LOADS];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int j = wid + r * kWaves;
+#pragma unroll
+      for (int q = 0; q < LOADS; ++q) {
+        const int idx = q0 + q * kWave + lane;
+        v[r][q] = (j < n && idx < nt) ? base[static_cast<size_t>(j) * nt + idx] : 0.0;
+      }
     }
 #pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
-      const int idx = q0 + q * kFieldA + tid;
-      // row of value idx (idx < 2^24: the float quotient is off by at most one)
-      int j = static_cast<int>(static_cast<float>(idx) * rnt);
-      j -= j * a.ntiles > idx ? 1 : 0;
-      j += (j + 1) * a.ntiles <= idx ? 1 : 0;
+    for (int r = 0; r < RW; ++r)
 #pragma unroll
-      for (int jj = 0; jj < kMaxN; ++jj)
-        if (jj == j) s[jj] += v[q];
-    }
+      for (int q = 0; q < LOADS; ++q) s[r] += v[r][q];
   }
 #pragma unroll
-  for (int j = 0; j < kMaxN; ++j) {
+  for (int r = 0; r < RW; ++r) {
+    const int j = wid + r * kWaves;
     if (j < n) {
-      const double d = wave_sum(s[j]);
-      if (lane == 0) red[wid][j] = d;
+      const double d = wave_sum(s[r]);
+      if (lane == 0) {
+        dens[j] = d;
+        a.dens[ix * n + j] = d;
+      }
     }
   }
   if (tid < n) wxs[tid] = wxj;
-  __syncthreads();
-  if (tid < n) {
-    double d = 0.0;
-    for (int w = 0; w < kFieldA / kWave; ++w) d += red[w][tid];
-    dens[tid] = d;
-    a.dens[ix * n + tid] = d;
-  }
   __syncthreads();
   for (int p = tid; p < a.pmax; p += kFieldA) {
     double cr = 0.0, ci = 0.0;
